@@ -1,0 +1,499 @@
+"""Pins of the FP64 reference implementation (CPU only).
+
+Each test checks the reference against something other than itself: the
+numbers the paper prints (Table I), closed forms (Porter-Thomas, uniform
+and point-mass distributions, Eq. (pal)), an independent method (the
+Ising path sum of App. C, brute-force Kronecker products, a stabilizer
+tableau, the parameter-shift rule) or invariants (norm, inverse circuit).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.stats
+
+import oracle
+from paper_1608_00263_amd import circuits as C
+from tests.stabilizer import run_clifford
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+EG = 0.57721566490153286061
+
+
+# --------------------------------------------------------------------------
+# generator: the printed gate counts of Table I and the Sec. IV rules
+# --------------------------------------------------------------------------
+def test_table1_gates_per_level():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "table1_gates_per_level.txt"))
+            if l.strip() and not l.startswith("#")]
+    for r, c, n, gpl in rows:
+        circ = C.make_circuit(int(r), int(c), 25, seed=7)
+        assert circ.n == int(n)
+        assert abs(circ.gates_per_level() - float(gpl)) <= 0.2, (r, c, circ.gates_per_level())
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(4, 4, 25, 1), (5, 6, 40, 2), (5, 7, 40, 5)])
+def test_generator_rules(rows, cols, depth, seed):
+    circ = C.make_circuit(rows, cols, depth, seed)
+    g = circ.gates
+    n = circ.n
+    assert (g["kind"][:n] == C.H).all() and (g["cycle"][:n] == 0).all()
+    last = {}
+    in_cz = {0: set()}
+    for t in range(1, depth + 1):
+        cyc = g[g["cycle"] == t]
+        cz = cyc[cyc["kind"] == C.CZ]
+        busy = set()
+        for a, b in zip(cz["q0"], cz["q1"]):
+            ra, ca = divmod(int(a), cols)
+            rb, cb = divmod(int(b), cols)
+            assert abs(ra - rb) + abs(ca - cb) == 1          # nearest neighbours
+            assert a not in busy and b not in busy
+            busy.update((int(a), int(b)))
+        # no two CZ of one layout on neighbouring qubits (Fig. 6 caption)
+        for a, b in zip(cz["q0"], cz["q1"]):
+            for c_, d_ in zip(cz["q0"], cz["q1"]):
+                if (a, b) == (c_, d_):
+                    continue
+                for u in (a, b):
+                    for v in (c_, d_):
+                        ru, cu = divmod(int(u), cols)
+                        rv, cv = divmod(int(v), cols)
+                        assert abs(ru - rv) + abs(cu - cv) > 1
+        in_cz[t] = busy
+        one = cyc[cyc["kind"] != C.CZ]
+        for k, q in zip(one["kind"], one["q0"]):
+            q = int(q)
+            assert q not in busy                      # idle this cycle
+            assert q in in_cz[t - 1]                  # in a CZ in the previous cycle
+            if q not in last:
+                assert k == C.T                       # first gate after H is T
+            else:
+                assert k != last[q]                   # differs from the last one
+            last[q] = int(k)
+    # every bond used exactly once per 8 cycles
+    if depth >= 8:
+        bonds = set()
+        for t in range(1, 9):
+            cyc = g[(g["cycle"] == t) & (g["kind"] == C.CZ)]
+            for a, b in zip(cyc["q0"], cyc["q1"]):
+                assert (a, b) not in bonds
+                bonds.add((a, b))
+        assert len(bonds) == rows * (cols - 1) + cols * (rows - 1)
+
+
+def test_splitmix64_published():
+    want = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert [oracle.splitmix64(0, i) for i in range(3)] == want
+    assert list(C.splitmix64_words(0, 3)) == want
+    # counter form seed + (i+1) gamma equals the sequential stream
+    assert [oracle.splitmix64(12345, i) for i in range(50)] == list(C.splitmix64_words(12345, 50))
+
+
+# --------------------------------------------------------------------------
+# gate matrices from their generators (independent construction)
+# --------------------------------------------------------------------------
+PX = np.array([[0, 1], [1, 0]], dtype=complex)
+PY = np.array([[0, -1j], [1j, 0]], dtype=complex)
+PZ = np.array([[1, 0], [0, -1]], dtype=complex)
+
+
+def rot(P, a):
+    return scipy.linalg.expm(-0.5j * a * P)
+
+
+def ph(a):
+    return np.exp(0.5j * a) * rot(PZ, a)          # diag(1, e^{ia})
+
+
+def indep_matrix(kind, th=0.0, mat=None):
+    pi = math.pi
+    return {
+        C.H: (PX + PZ) / math.sqrt(2), C.T: ph(pi / 4 + th), C.TDG: ph(-pi / 4 + th),
+        C.S: ph(pi / 2), C.SDG: ph(-pi / 2), C.Z: PZ, C.X: PX, C.Y: PY,
+        C.SX: rot(PX, pi / 2 + th), C.SXDG: rot(PX, -pi / 2 + th),
+        C.SY: rot(PY, pi / 2 + th), C.SYDG: rot(PY, -pi / 2 + th),
+    }[kind] if kind != C.U1 else mat
+
+
+@pytest.mark.parametrize("kind", [k for k in range(13) if k != C.CZ])
+def test_gate_matrices(kind):
+    for th in ([0.0, 0.3, -1.1] if kind in C.PARAMETRISABLE else [0.0]):
+        u = oracle.gate_matrix(kind, th)
+        np.testing.assert_allclose(u, indep_matrix(kind, th), atol=1e-14)
+        np.testing.assert_allclose(u.conj().T @ u, np.eye(2), atol=1e-14)
+
+
+def test_gate_phase_conventions_app_c():
+    # Eq. (phX): X^1/2 adds phase pi/2 when the spin is unchanged, so the
+    # diagonal/off-diagonal ratio is i; Eq. (phY): Y^1/2 adds pi only on
+    # the 1 -> 0 transition; Eq. (phT): T adds pi/4 on state 1.
+    sx = oracle.gate_matrix(C.SX)
+    assert abs(sx[0, 0] / sx[0, 1] - 1j) < 1e-14 and abs(sx[1, 1] / sx[1, 0] - 1j) < 1e-14
+    sy = oracle.gate_matrix(C.SY)
+    assert abs(sy[0, 1] / sy[0, 0] + 1) < 1e-14
+    assert abs(sy[1, 0] / sy[0, 0] - 1) < 1e-14 and abs(sy[1, 1] / sy[0, 0] - 1) < 1e-14
+    t = oracle.gate_matrix(C.T)
+    assert abs(t[1, 1] / t[0, 0] - np.exp(1j * math.pi / 4)) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# state evolution
+# --------------------------------------------------------------------------
+def full_operator(n, kind, q0, q1, th, mat):
+    if kind == C.CZ:
+        d = np.ones(1 << n, dtype=complex)
+        idx = np.arange(1 << n)
+        d[((idx >> q0) & 1) & ((idx >> q1) & 1) == 1] = -1
+        return np.diag(d)
+    g = indep_matrix(kind, th, mat)
+    return np.kron(np.kron(np.eye(1 << (n - q0 - 1)), g), np.eye(1 << q0))
+
+
+def brute_force_state(circ):
+    n = circ.n
+    U = np.eye(1 << n, dtype=complex)
+    for g in circ.gates:
+        p = int(g["param"])
+        th = circ.theta[p] if p >= 0 else 0.0
+        mat = circ.mats[int(g["mat"])] if int(g["mat"]) >= 0 else None
+        U = full_operator(n, int(g["kind"]), int(g["q0"]), int(g["q1"]), th, mat) @ U
+    return U[:, 0]
+
+
+@pytest.mark.parametrize("case", ["paper23", "paper32_par", "random5", "random6"])
+def test_bruteforce_kron(case):
+    if case == "paper23":
+        circ = C.make_circuit(2, 3, 14, seed=11)
+    elif case == "paper32_par":
+        circ = C.make_circuit(3, 2, 12, seed=12, parametrise=True, theta_seed=5, theta_std=0.7)
+    elif case == "random5":
+        circ = C.random_unitary_circuit(5, 80, seed=13)
+    else:
+        circ = C.random_unitary_circuit(6, 120, seed=14)
+    psi = oracle.apply_circuit(circ)
+    np.testing.assert_allclose(psi, brute_force_state(circ), atol=1e-13)
+
+
+def ising_path_sum(circ):
+    """<x|psi> from the path integral of App. C (Eqs. (path1), (phX), (phY),
+    (phT), (phCZ)): each path is a sequence of bits per qubit, one after
+    each two-sparse gate (H, X^1/2, Y^1/2); its phase, in units of pi/4,
+    collects +2 for an X^1/2 that keeps the bit, +4 for a Y^1/2 taking 1 to
+    0, +1 for a T on a qubit in state 1 and +4 for a CZ on two qubits in
+    state 1.  Every two-sparse gate contributes magnitude 2^-1/2, and the
+    phase each X^1/2 leaves out is the constant -i (= -2 units)."""
+    n = circ.n
+    kinds = circ.gates["kind"]
+    assert set(np.unique(kinds)) <= {C.H, C.CZ, C.T, C.SX, C.SY}
+    ng = [0] * n
+    for g in circ.gates:
+        if int(g["kind"]) in (C.H, C.SX, C.SY):
+            ng[int(g["q0"])] += 1
+    col = {}
+    nfree = 0
+    for j in range(n):
+        for k in range(ng[j] - 1):
+            col[(j, k)] = nfree
+            nfree += 1
+    for j in range(n):
+        col[(j, ng[j] - 1)] = nfree + j          # last bit = output bit x_j
+    ncol = nfree + n
+    rows = np.arange(1 << ncol, dtype=np.int64)
+    bit = lambda c: ((rows >> c) & 1).astype(np.int64)
+    cur = [-1] * n
+    units = np.zeros(rows.size, dtype=np.int64)
+    nx = 0
+    nts = 0
+    for g in circ.gates:
+        k, a, b = int(g["kind"]), int(g["q0"]), int(g["q1"])
+        if k in (C.H, C.SX, C.SY):
+            nts += 1
+            prev = bit(col[(a, cur[a])]) if cur[a] >= 0 else None
+            cur[a] += 1
+            new = bit(col[(a, cur[a])])
+            if k == C.SX:
+                nx += 1
+                units += 2 * (prev == new)
+            elif k == C.SY:
+                units += 4 * ((prev == 1) & (new == 0))
+        elif k == C.T:
+            units += bit(col[(a, cur[a])])
+        elif k == C.CZ:
+            units += 4 * (bit(col[(a, cur[a])]) & bit(col[(b, cur[b])]))
+    terms = np.exp(1j * math.pi / 4 * (units - 2 * nx)) * 2.0 ** (-nts / 2)
+    x = rows >> nfree
+    return np.bincount(x, weights=terms.real, minlength=1 << n) + \
+        1j * np.bincount(x, weights=terms.imag, minlength=1 << n)
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(2, 2, 10, 3), (2, 3, 9, 4), (3, 2, 8, 5)])
+def test_ising_path_sum(rows, cols, depth, seed):
+    circ = C.make_circuit(rows, cols, depth, seed)
+    psi = oracle.apply_circuit(circ)
+    np.testing.assert_allclose(psi, ising_path_sum(circ), atol=1e-12)
+
+
+def test_norm_and_inverse():
+    circ = C.make_circuit(4, 4, 25, seed=1)
+    psi = oracle.zero_state(circ.n)
+    for i in range(circ.ngates):
+        oracle.apply_circuit(circ, psi, i, i + 1)
+        assert abs(np.vdot(psi, psi).real - 1.0) < 1e-13
+    back = oracle.apply_circuit(circ.inverse(), psi)
+    e0 = np.zeros_like(back)
+    e0[0] = 1
+    np.testing.assert_allclose(back, e0, atol=1e-13)
+    pc = C.make_circuit(3, 4, 10, seed=2, parametrise=True, theta_seed=3, theta_std=0.4)
+    psi = oracle.apply_circuit(pc)
+    back = oracle.apply_circuit(pc.inverse(), psi)
+    e0 = np.zeros_like(back)
+    e0[0] = 1
+    np.testing.assert_allclose(back, e0, atol=1e-13)
+
+
+def test_diagonal_prefix_is_uniform():
+    # cycles 0..3 hold only H, CZ and T (the first X^1/2 or Y^1/2 can come
+    # at cycle 4), so the output stays uniform (Sec. IV, Fig. 7 discussion)
+    circ = C.make_circuit(4, 5, 40, seed=9)
+    pre = circ.prefix_cycles(3)
+    assert set(np.unique(pre.gates["kind"])) <= {C.H, C.CZ, C.T}
+    p = oracle.probs(oracle.apply_circuit(pre))
+    np.testing.assert_allclose(p * p.size, 1.0, atol=1e-12)
+    p4 = oracle.probs(oracle.apply_circuit(circ.prefix_cycles(5)))
+    assert np.abs(p4 * p4.size - 1).max() > 0.1
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(3, 4, 16, 21), (4, 4, 20, 22), (2, 5, 30, 23)])
+def test_clifford_vs_tableau(rows, cols, depth, seed):
+    circ = C.make_circuit(rows, cols, depth, seed, clifford=True)
+    psi = oracle.apply_circuit(circ)
+    p = oracle.probs(psi)
+    tab = run_clifford(circ)
+    r = tab.num_random()
+    support = p > 0.5 * 2.0 ** (-r)
+    assert support.sum() == 2 ** r
+    np.testing.assert_allclose(p[support], 2.0 ** (-r), rtol=1e-12)
+    assert p[~support].max(initial=0.0) < 1e-20
+    rs = np.random.default_rng(seed)
+    xs = list(rs.choice(np.nonzero(support)[0], 24)) + list(rs.integers(0, p.size, 24))
+    for x in xs:
+        bits = [(int(x) >> q) & 1 for q in range(circ.n)]
+        assert abs(tab.probability(bits) - p[x]) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# statistics: closed forms
+# --------------------------------------------------------------------------
+def test_stats_uniform_and_point_mass():
+    N = 1 << 12
+    st = oracle.stats(np.full(N, 1.0 / N))
+    assert abs(st["norm"] - 1) < 1e-14
+    assert abs(st["entropy"] - math.log(N)) < 1e-12
+    assert abs(st["unif_ce"] - math.log(N)) < 1e-12
+    np.testing.assert_allclose(st["moments"], 1.0, rtol=1e-12)
+    pm = np.zeros(N)
+    pm[77] = 1.0
+    st = oracle.stats(pm)
+    assert st["entropy"] == 0.0
+    assert st["unif_ce"] == math.inf and st["zero_count"] == N - 1
+    np.testing.assert_allclose(st["moments"], [float(N) ** (k - 1) for k in range(1, 11)], rtol=1e-12)
+
+
+def test_stats_two_level_and_scaling():
+    N = 1 << 11
+    p = np.empty(N)
+    p[::2] = 1.5 / N
+    p[1::2] = 0.5 / N
+    st = oracle.stats(p)
+    H = math.log(N) - 0.5 * (1.5 * math.log(1.5) + 0.5 * math.log(0.5))
+    assert abs(st["entropy"] - H) < 1e-12
+    assert abs(st["unif_ce"] - (math.log(N) - 0.5 * (math.log(1.5) + math.log(0.5)))) < 1e-12
+    np.testing.assert_allclose(st["moments"], [(1.5 ** k + 0.5 ** k) / 2 for k in range(1, 11)],
+                               rtol=1e-12)
+    st2 = oracle.stats(2.0 * p)
+    assert abs(st2["norm"] - 2.0) < 1e-13
+    for key in ("entropy", "unif_ce"):
+        assert abs(st2[key] - st[key]) < 1e-12
+    np.testing.assert_allclose(st2["moments"], st["moments"], rtol=1e-12)
+
+
+def test_stats_dirichlet_expectations():
+    # Porter-Thomas vectors are Dirichlet(1..1) (Sec. II): E[H] = H_N - 1,
+    # E[M_2] = 2N/(N+1), E[H_unif] = H_{N-1}; the spread of H is ~0.54 2^{-n/2}
+    n, reps = 14, 12
+    N = 1 << n
+    HN = float(np.sum(1.0 / np.arange(1, N + 1)))
+    Hs, M2, Hu = [], [], []
+    for s in range(reps):
+        st = oracle.stats(C.random_probabilities(N, 100 + s))
+        Hs.append(st["entropy"])
+        M2.append(st["M2"])
+        Hu.append(st["unif_ce"])
+    sig = 0.6 * 2 ** (-n / 2) / math.sqrt(reps)
+    assert abs(np.mean(Hs) - (HN - 1)) < 4 * sig
+    assert abs(np.mean(M2) - 2 * N / (N + 1)) < 4 * math.sqrt(20.0 / N / reps)
+    assert abs(np.mean(Hu) - (HN - 1.0 / N)) < 4 * math.sqrt((math.pi ** 2 / 6) / N / reps)
+    # ln N - 1 + gamma (Eq. (eu)) agrees with H_N - 1 to O(1/N)
+    assert abs((HN - 1) - (math.log(N) - 1 + EG)) < 1.0 / N
+
+
+def test_stats_bruteforce_small():
+    p = C.random_probabilities(1 << 10, 5, zeros=3)
+    st = oracle.stats(p)
+    N = p.size
+    S = math.fsum(p)
+    nz = p[p > 0]
+    assert st["zero_count"] == 3 and st["unif_ce"] == math.inf
+    assert abs(st["entropy"] - (math.log(S) - math.fsum(nz * np.log(nz)) / S)) < 1e-13
+    for k in range(1, 11):
+        want = math.fsum((N * p) ** k) / N / S ** k
+        assert abs(st["M%d" % k] / want - 1) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# sampler
+# --------------------------------------------------------------------------
+def test_sampler_two_point_closed_form():
+    # w = (2^60, 3 * 2^60), W = 2^62, t = r >> 2: index 0 exactly when r < 2^62
+    words = C.splitmix64_words(99, 4000)
+    x = oracle.sample_from_words(np.array([0.25, 0.75]), words)
+    np.testing.assert_array_equal(x, (words >= np.uint64(1 << 62)).astype(np.uint64))
+
+
+def test_sampler_definition_small():
+    p = C.random_probabilities(37, 8, zeros=5)
+    words = C.splitmix64_words(4, 3000)
+    x = oracle.sample_from_words(p, words)
+    w = [int(math.floor(math.ldexp(v, 62))) for v in p]
+    cdf = np.cumsum(np.array(w, dtype=object))
+    W = int(cdf[-1])
+    for r, xi in zip(words, x):
+        t = (int(r) * W) >> 64
+        j = next(j for j in range(len(w)) if cdf[j] > t)
+        assert j == xi
+    assert all(p[int(v)] > 0 for v in x)
+    np.testing.assert_array_equal(oracle.sample(p, 3000, 4), x)
+
+
+def test_sampler_frequencies():
+    p = C.random_probabilities(256, 17)
+    m = 200000
+    x = oracle.sample(p, m, 2024)
+    counts = np.bincount(x.astype(np.int64), minlength=p.size)
+    chi2 = float(((counts - m * p) ** 2 / (m * p)).sum())
+    assert scipy.stats.chi2.sf(chi2, p.size - 1) > 1e-4
+
+
+# --------------------------------------------------------------------------
+# deep circuits: Porter-Thomas (Sec. II) and Eq. (pal)
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c1_probs():
+    circ = C.make_circuit(4, 4, 25, seed=1)
+    return oracle.probs(oracle.apply_circuit(circ))
+
+
+def test_porter_thomas_c1(c1_probs):
+    p = c1_probs
+    n = 16
+    N = 1 << n
+    st = oracle.stats(p)
+    HN = float(np.sum(1.0 / np.arange(1, N + 1)))
+    sigH = 0.54 * 2 ** (-n / 2)
+    assert abs(st["entropy"] - (HN - 1)) < 4 * sigH
+    assert abs(st["unif_ce"] - (math.log(N) + EG)) < 4 * math.sqrt(math.pi ** 2 / 6 / N)
+    for k in range(2, 6):
+        fk = math.factorial(k)
+        sd = math.sqrt((math.factorial(2 * k) - fk * fk) / N)
+        assert abs(st["M%d" % k] - fk) < 4 * sd
+
+
+def test_eq_pal_ideal_and_uniform_samples(c1_probs):
+    p = c1_probs
+    N = p.size
+    m = 5000
+    x = oracle.sample(p, m, 1001).astype(np.int64)
+    z = np.log(N * p[x])
+    # alpha = 1: density e^{2z - e^z}, CDF 1 - (1 + e^z) e^{-e^z}
+    D = scipy.stats.kstest(z, lambda v: 1 - (1 + np.exp(v)) * np.exp(-np.exp(v))).statistic
+    assert D < 1.95 / math.sqrt(m)
+    xu = np.random.default_rng(3).integers(0, N, m)
+    zu = np.log(N * p[xu])
+    # alpha = 0: Gumbel-type law e^{z - e^z}, CDF 1 - e^{-e^z}
+    Du = scipy.stats.kstest(zu, lambda v: 1 - np.exp(-np.exp(v))).statistic
+    assert Du < 1.95 / math.sqrt(m)
+
+
+def test_cross_entropy_closed_forms(c1_probs):
+    N = 1 << 12
+    x = np.arange(0, N, 3, dtype=np.uint64)
+    ce, dh, z = oracle.cross_entropy(np.full(N, 1.0 / N), x)
+    assert abs(ce - math.log(N)) < 1e-12 and abs(dh - EG) < 1e-12 and z == 0
+    p = c1_probs
+    m = 10000
+    xs = oracle.sample(p, m, 1001)
+    ce, dh, z = oracle.cross_entropy(p, xs)
+    st = oracle.stats(p)
+    sd = math.sqrt(math.pi ** 2 / 6 - 1) / math.sqrt(m)
+    assert abs(ce - st["entropy"]) < 5 * sd
+    assert abs(dh - 1.0) < 5 * sd + 0.01
+    pz = p.copy()
+    pz[int(xs[0])] = 0.0
+    ce, dh, z = oracle.cross_entropy(pz, xs)
+    assert ce == math.inf and z >= 1
+
+
+# --------------------------------------------------------------------------
+# adjoint gradient: parameter-shift rule and central differences
+# --------------------------------------------------------------------------
+def loss_of(circ, xs):
+    p = oracle.probs(oracle.apply_circuit(circ))
+    return -float(np.mean(np.log(p[xs.astype(np.int64)]))), p
+
+
+def test_adjoint_parameter_shift():
+    circ = C.make_circuit(3, 3, 10, seed=31, parametrise=True, theta_seed=32, theta_std=0.05)
+    nominal = circ.with_theta(np.zeros(circ.nparams))
+    p0 = oracle.probs(oracle.apply_circuit(nominal))
+    xs = oracle.sample(p0, 300, 1004)
+    loss, grad = oracle.adjoint(circ, xs)
+    L, p = loss_of(circ, xs)
+    assert abs(loss - L) < 1e-12
+    xi = xs.astype(np.int64)
+    shift = np.zeros(circ.nparams)
+    for g in range(circ.nparams):
+        th = circ.theta.copy()
+        th[g] += math.pi / 2
+        pp = oracle.probs(oracle.apply_circuit(circ.with_theta(th)))
+        th[g] -= math.pi
+        pm = oracle.probs(oracle.apply_circuit(circ.with_theta(th)))
+        dp = 0.5 * (pp[xi] - pm[xi])
+        shift[g] = -np.mean(dp / p[xi])
+    np.testing.assert_allclose(grad, shift, atol=1e-10 * max(1.0, np.abs(shift).max()))
+
+
+def test_adjoint_central_difference():
+    circ = C.make_circuit(4, 4, 12, seed=41, parametrise=True, theta_seed=42, theta_std=0.05)
+    p0 = oracle.probs(oracle.apply_circuit(circ.with_theta(np.zeros(circ.nparams))))
+    xs = oracle.sample(p0, 2000, 1005)
+    loss, grad = oracle.adjoint(circ, xs)
+    rs = np.random.default_rng(0)
+
+    def central(g, h):
+        th = circ.theta.copy()
+        th[g] += h
+        lp, _ = loss_of(circ.with_theta(th), xs)
+        th[g] -= 2 * h
+        lm, _ = loss_of(circ.with_theta(th), xs)
+        return (lp - lm) / (2 * h)
+
+    for g in rs.choice(circ.nparams, 8, replace=False):
+        f1, f2 = central(g, 1e-4), central(g, 2e-4)
+        # central difference at h = 1e-4: O(h^2) truncation, here ~1e-7
+        assert abs(f1 - grad[g]) < 1e-6 * max(1.0, abs(grad[g]))
+        # Richardson extrapolation removes the h^2 term
+        assert abs((4 * f1 - f2) / 3 - grad[g]) < 1e-8 * max(1.0, abs(grad[g]))
