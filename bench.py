@@ -1,0 +1,229 @@
+"""Benchmark of the hot path on one MI355X.
+
+One step = the whole path over one synthetic input: simulate the 5x6-grid,
+30-qubit, depth-40 random circuit of Sec. IV from |0...0> in complex64
+(fused register-tile sweeps), compute the output statistics (entropy,
+uniform cross entropy, moments 1..10), draw 10^5 samples and evaluate
+their cross entropy.  Prints one JSON line.
+
+value      = algorithmic HBM bytes of the step / step time (GB/s); the
+             bytes are the sweeps' reads + writes of the state, one state
+             read for the statistics, two for the sampler, and the sample
+             gathers;
+roofline   = the dominant kernel (register-tile sweep), its algorithmic
+             bytes per launch over its event-timed average duration;
+circuit_s  = seconds of the same circuit per planning mode (plain per-gate,
+             specialised per-gate, fused 2^k blocks, LDS tiles, register
+             tiles) in complex64 and complex128;
+grad       = adjoint gradient time over forward time on the 5x5, depth-30
+             parametrised circuit (10^4 samples) for checkpoint intervals;
+cpu_baseline = the FP64 reference timed on this host on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+
+
+def log(msg):
+    sys.stderr.write("[bench] %s\n" % msg)
+    sys.stderr.flush()
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", default="regtile")
+    ap.add_argument("--tile", type=int, default=6)
+    ap.add_argument("--samples", type=int, default=100000)
+    ap.add_argument("--no-modes", action="store_true", help="skip the per-mode circuit timings")
+    ap.add_argument("--no-grad", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(circ, budget_s):
+    """The FP64 reference on this host: gates of the 30-qubit circuit,
+    complex128, one plain sweep per gate, until the time budget is used."""
+    import numpy as np
+    import oracle
+    n = circ.n
+    psi = oracle.zero_state(n)
+    S = 16.0 * 2 ** n
+    done = 0
+    t0 = time.perf_counter()
+    while done < circ.ngates and time.perf_counter() - t0 < budget_s:
+        oracle.apply_circuit(circ, psi, done, done + 1)
+        done += 1
+    dt = time.perf_counter() - t0
+    del psi
+    return {"value": round(2 * S * done / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "first %d of %d gates of the 5x6 depth-40 circuit, 30 qubits, complex128, "
+                      "one plain sweep per gate (%.1f s); GB/s = 2 x 16 GiB x gates / time"
+                      % (done, circ.ngates, dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1608_00263_amd import circuits as C
+    from paper_1608_00263_amd import sv
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    dev_name = torch.cuda.get_device_name(0)
+    circ = C.make_circuit(5, 6, 40, seed=2)
+    n = circ.n
+    S64 = 8.0 * 2 ** n
+    args = sv.CircuitArgs(circ)
+    st = sv.State(n, "c64")
+    m = a.samples
+
+    def step():
+        ms, kinds, by = st.apply_timed(circ, a.mode, 0, a.tile, args=args, from_zero=True)
+        mom = st.moments()
+        xs = st.sample(m, 1002)
+        ce, dh, z = st.cross_entropy(xs)
+        return ms, kinds, by, mom, ce, dh
+
+    log("device %s; circuit 5x6 d40: %d gates" % (dev_name, circ.ngates))
+    for i in range(a.warmup):
+        step()
+        log("warmup %d done" % i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sweep_ms = []
+    sweep_bytes = []
+    dom_ms = 0.0
+    dom_bytes = 0.0
+    dom_launches = 0
+    last = None
+    for i in range(a.steps):
+        ms, kinds, by, mom, ce, dh = step()
+        sweep_ms.append(float(ms.sum()))
+        sweep_bytes.append(float(by.sum()))
+        sel = kinds == 8        # register-tile sweeps
+        dom_ms += float(ms[sel].sum())
+        dom_bytes += float(by[sel].sum())
+        dom_launches += int(sel.sum())
+        last = (mom, ce, dh, len(ms))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    step_s = (t1 - t0) / a.steps
+    mom, ce, dh, nsweeps = last
+    step_bytes = sweep_bytes[-1] + S64 + 2 * S64 + m * 128.0
+    value = step_bytes / step_s / 1e9
+    achieved = dom_bytes / (dom_ms / 1e3) / 1e9
+    log("timed %d steps: %.2f ms/step, sweeps %.2f ms, %d sweeps" % (a.steps, step_s * 1e3,
+                                                                        np.mean(sweep_ms), nsweeps))
+    out = {
+        "metric": "HBM GB/s (% peak) of gate sweeps; 30q d40 circuit sec fused vs plain; grad/fwd",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(step_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "random lattice circuit, 5x6 grid = 30 qubits, depth 40 (625 gates), "
+                               "complex64 state, statistics + 1e5 samples + their cross entropy",
+                   "mode": a.mode, "register_qubits": a.tile, "sweeps": nsweeps},
+        "sweep_GBps": round(sweep_bytes[-1] / (np.mean(sweep_ms) / 1e3) / 1e9, 2),
+        "sweep_frac_of_peak": round(sweep_bytes[-1] / (np.mean(sweep_ms) / 1e3) / 1e9 / PEAK_HBM_GBPS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "kernel": "k_regtile<float,%d>" % a.tile,
+                     "launch_avg_ms": round(dom_ms / max(dom_launches, 1), 4),
+                     "bytes_per_launch": 2 * S64},
+        "results": {"entropy": mom["entropy"], "unif_ce": mom["unif_ce"], "norm": mom["norm"],
+                    "M2": mom["M2"], "M10": mom["M10"], "ce": ce, "delta_h": dh},
+    }
+    if not a.no_modes:
+        out["circuit_s"] = mode_timings(sv, C, circ, torch)
+    if not a.no_grad:
+        out["grad"] = grad_timings(sv, C, torch)
+    st.close()
+    del st
+    torch.cuda.empty_cache()
+    if not a.no_cpu:
+        log("cpu baseline (%.0f s budget)" % a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(circ, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def mode_timings(sv, C, circ, torch):
+    res = {}
+    for dtype in ("c64", "c128"):
+        st = sv.State(circ.n, dtype)
+        args = sv.CircuitArgs(circ)
+        modes = [("plain", 0, 0), ("spec", 0, 0), ("fused", 2, 0), ("fused", 3, 0), ("fused", 4, 0),
+                 ("fused", 5, 0), ("tiled", 4, 13 if dtype == "c64" else 12),
+                 ("regtile", 0, 5), ("regtile", 0, 6 if dtype == "c64" else 5)]
+        for mode, k, t in modes:
+            st.apply(circ, mode, k, t, args=args, from_zero=True)   # plan + warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.apply(circ, mode, k, t, args=args, from_zero=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            sw, by = st.plan_info(circ, mode, k, t)
+            key = "%s_%s%s" % (dtype, mode, ("_k%d" % k if k else "") + ("_t%d" % t if t else ""))
+            res[key] = {"s": round(dt, 4), "sweeps": sw, "GBps": round(by / dt / 1e9, 1)}
+            log("%s: %.3f s, %d sweeps" % (key, dt, sw))
+        st.close()
+        del st
+        torch.cuda.empty_cache()
+    return res
+
+
+def grad_timings(sv, C, torch):
+    import numpy as np
+    circ = C.make_circuit(5, 5, 30, seed=4, parametrise=True, theta_seed=4004, theta_std=0.05)
+    nominal = circ.with_theta(np.zeros(circ.nparams))
+    st = sv.State(circ.n, "c64")
+    st.apply(nominal, "regtile", 0, 5, from_zero=True)
+    xs = st.sample(10000, 1004)
+    args = sv.CircuitArgs(circ)
+    st.apply(circ, "regtile", 0, 5, args=args, from_zero=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        st.apply(circ, "regtile", 0, 5, args=args, from_zero=True)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / 3
+    out = {"workload": "5x5 grid, 25 qubits, depth 30, %d parametrised gates, complex64, 1e4 samples"
+                       % circ.nparams, "forward_s": round(fwd, 5)}
+    for ck in (0, 5, 10):
+        st.backward(circ, xs, checkpoint_c=ck)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss, g = st.backward(circ, xs, checkpoint_c=ck)
+        dt = time.perf_counter() - t0
+        out["c%d" % ck] = {"grad_s": round(dt, 5), "grad_over_fwd": round(dt / fwd, 3), "loss": loss}
+        log("grad c=%d: %.4f s (fwd %.4f s)" % (ck, dt, fwd))
+    st.close()
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,233 @@
+/*
+ * sv.h -- C ABI of the MI355X (gfx950) state-vector library for the random
+ * lattice circuits of Boixo et al., "Characterizing Quantum Supremacy in
+ * Near-Term Devices" (arXiv:1608.00263).
+ *
+ * The library evolves a 2^n amplitude state on one GPU (Sec. II: the output
+ * |psi> = U|psi_0> of a random circuit U, psi_0 = |0...0>), and computes the
+ * quantities the paper defines on its output distribution p_U(x) = |<x|psi>|^2:
+ * probabilities, entropy, cross entropy with the uniform distribution, the
+ * normalised moments N^{k-1} sum_x p^k, bit-string samples and their cross
+ * entropy (the estimator of Eq. (ae)), plus the gradient of the sample cross
+ * entropy with respect to per-gate rotation offsets.
+ *
+ * Conventions shared by every call
+ *  - Qubit q is bit q of an amplitude index and of a sample (uint64).
+ *  - All logarithms are natural (nats).
+ *  - Every call returns an sv_status; nothing throws across the ABI.  On a
+ *    non-OK status sv_last_error() returns a message (per thread).
+ *  - Every device operation is enqueued on the stream of the state handle;
+ *    calls that return host scalars synchronise that stream first.
+ *  - Pointers are host pointers unless a parameter says "device".
+ */
+#ifndef SV_ABI_H_INCLUDED
+#define SV_ABI_H_INCLUDED
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SV_OK = 0,
+    SV_EINVAL = -1,   /* bad argument: qubit, kind, n mismatch, null pointer  */
+    SV_ENOMEM = -2,   /* not enough device (or host) memory                  */
+    SV_EDEVICE = -3,  /* a HIP runtime call failed (message has the details) */
+    SV_ERANGE = -4,   /* size out of range (n, chunk, sample count)          */
+    SV_ESTATE = -5    /* call not valid in the handle's current state        */
+} sv_status;
+
+typedef enum { SV_C64 = 0, SV_C128 = 1 } sv_dtype;
+
+/* Gate kinds (Sec. IV gate set plus what tests and inverses need).
+ * H = Hadamard; CZ = diag(1,1,1,-1); T = diag(1, e^{i pi/4});
+ * SX = X^1/2 = RX(pi/2); SY = Y^1/2 = RY(pi/2), with
+ * RX(a) = [[cos a/2, -i sin a/2], [-i sin a/2, cos a/2]],
+ * RY(a) = [[cos a/2, -sin a/2], [sin a/2, cos a/2]], P(a) = diag(1, e^{ia});
+ * S = P(pi/2); X, Y, Z Paulis; *_DG the adjoints; U1 a dense 2x2 taken from
+ * sv_circuit.mats.  A gate with param >= 0 is a rotation with angle
+ * nominal + theta[param]: T -> P(pi/4 + t), SX -> RX(pi/2 + t),
+ * SY -> RY(pi/2 + t), TDG -> P(-pi/4 + t), SXDG -> RX(-pi/2 + t),
+ * SYDG -> RY(-pi/2 + t); other kinds must have param = -1. */
+typedef enum {
+    SV_H = 0, SV_CZ = 1, SV_T = 2, SV_SX = 3, SV_SY = 4, SV_S = 5,
+    SV_X = 6, SV_Y = 7, SV_Z = 8, SV_TDG = 9, SV_SDG = 10, SV_SXDG = 11,
+    SV_SYDG = 12, SV_U1 = 13
+} sv_kind;
+
+/* One gate record (24 bytes).  q1 is the second qubit of CZ, else -1.
+ * cycle is the clock cycle (0 = the Hadamard layer); it bounds the
+ * adjoint's checkpoints and is otherwise informational.  mat indexes
+ * sv_circuit.mats for SV_U1, else -1. */
+typedef struct {
+    int32_t kind, q0, q1, cycle, param, mat;
+} sv_gate;
+
+/* A circuit.  Owned by the caller; the library copies what it keeps. */
+typedef struct {
+    int32_t n;               /* qubits                                         */
+    int32_t nparams;         /* length of theta (0 if none)                    */
+    int64_t ngates;
+    const sv_gate *gates;
+    const double *theta;     /* rotation offsets, may be NULL if nparams == 0  */
+    int32_t nmats;
+    int32_t reserved;
+    const double *mats;      /* nmats 2x2 complex128 matrices, row-major,
+                                (re, im) interleaved: 8 doubles per matrix     */
+} sv_circuit;
+
+/* How sv_apply_circuit maps gates onto sweeps over the state (a sweep reads
+ * and writes the state once):
+ *  SV_MODE_PLAIN    one sweep per gate, every gate as a dense 2x2 (CZ as a
+ *                   controlled-Z on the pairs whose control bit is set);
+ *  SV_MODE_SPEC     one sweep per gate with specialised kernels (diagonal
+ *                   gates touch only the lines they change, H is real);
+ *  SV_MODE_FUSED    gates fused into dense 2^k x 2^k unitaries (k <= k_max,
+ *                   diagonal gates folded in), one LDS-staged sweep each;
+ *                   k >= 4 blocks run on the matrix cores (complex64);
+ *  SV_MODE_TILED    the fused blocks grouped into LDS tile sweeps of
+ *                   2^tile_qubits amplitudes (several blocks per sweep);
+ *  SV_MODE_REGTILE  gates applied one by one inside register tiles (qubits
+ *                   0..5 across the 64 lanes of a wavefront, a few gathered
+ *                   qubits in registers), diagonal gates folded;
+ *  SV_MODE_AUTO     time candidate plans once per circuit shape and keep
+ *                   the fastest (autotuner; results cached per process). */
+enum {
+    SV_MODE_PLAIN = 0, SV_MODE_SPEC = 1, SV_MODE_FUSED = 2,
+    SV_MODE_TILED = 3, SV_MODE_REGTILE = 4, SV_MODE_AUTO = 5
+};
+
+/* sv_opts.flags bits */
+enum {
+    SV_FLAG_FROM_ZERO = 1   /* ignore the current contents: simulate U|0...0> */
+};
+
+typedef struct {
+    int32_t mode;         /* SV_MODE_*                                        */
+    int32_t k_max;        /* fused block width 1..5 (0 = default 4)           */
+    int32_t tile_qubits;  /* TILED: 8..13 (0 = default); REGTILE: register
+                             qubits 1..6 (0 = default)                        */
+    int32_t flags;        /* SV_FLAG_* bits                                   */
+} sv_opts;
+
+/* Output statistics of p_hat = p / S (Secs. II and IV):
+ *  norm      S = sum_x p(x)
+ *  entropy   H = -sum p_hat ln p_hat              (Eq. (lps) definition)
+ *  unif_ce   -(1/N) sum ln p_hat(x): cross entropy of the uniform sampler
+ *            with the output (Eq. (15) with p_cl = 1/N); +inf if some p = 0
+ *  moments   moments[k-1] = M_k = (1/N) sum (N p_hat)^k = N^{k-1} IPR_k,
+ *            k = 1..10 (Porter-Thomas: M_k -> k!)
+ *  zero_count  number of x with p(x) = 0 */
+typedef struct {
+    double norm, entropy, unif_ce;
+    double moments[10];
+    int64_t zero_count;
+} sv_stats;
+
+typedef struct sv_state sv_state;   /* opaque handle */
+
+/* Allocate a 2^n state in device memory owned by the library and set it to
+ * |0...0>.  n in 1..35 for SV_C64, 1..34 for SV_C128 (else SV_ERANGE);
+ * SV_ENOMEM if the device cannot hold it.  hip_stream may be NULL (the
+ * null stream).  The handle is freed with sv_free. */
+sv_status sv_alloc(int n, sv_dtype dt, void *hip_stream, sv_state **out);
+
+/* Wrap a caller-owned device buffer of 2^n interleaved complex amplitudes
+ * (float2 for SV_C64, double2 for SV_C128).  The buffer's contents are the
+ * state; it must outlive the handle and is never freed by the library. */
+sv_status sv_attach(int n, sv_dtype dt, void *dev_ptr, void *hip_stream, sv_state **out);
+
+sv_status sv_free(sv_state *st);
+
+/* Set the state to |0...0> (Sec. II, psi_0). */
+sv_status sv_reset(sv_state *st);
+
+/* Device pointer of the amplitudes (interleaved re, im). */
+sv_status sv_data(sv_state *st, void **dev_ptr);
+
+/* Apply the gates of c in list order to the state, in place (asynchronous
+ * on the handle's stream).  The single-qubit update is that of App. B,
+ * Eq. (sqgunitaryoperation); CZ is the controlled phase of Sec. IV.
+ * opts may be NULL (SV_MODE_AUTO).  SV_EINVAL for an invalid gate or
+ * c->n != n.  Plans are cached per circuit. */
+sv_status sv_apply_circuit(sv_state *st, const sv_circuit *c, const sv_opts *opts);
+
+/* Number of sweeps over the state the plan for (c, opts) performs, and the
+ * algorithmic bytes it moves (reads + writes of the state). */
+sv_status sv_plan_info(sv_state *st, const sv_circuit *c, const sv_opts *opts,
+                       int64_t *sweeps, double *bytes);
+
+/* Sweep kinds reported by sv_apply_circuit_timed. */
+enum {
+    SV_SWEEP_INIT = 1, SV_SWEEP_PLAIN_1Q = 2, SV_SWEEP_PLAIN_CZ = 3, SV_SWEEP_SPEC_DENSE = 4,
+    SV_SWEEP_SPEC_REAL = 5, SV_SWEEP_SPEC_DIAG = 6, SV_SWEEP_SPEC_CZ = 7, SV_SWEEP_REGTILE = 8,
+    SV_SWEEP_LDSTILE = 9, SV_SWEEP_LDSTILE_MFMA = 10
+};
+
+/* sv_apply_circuit with a HIP event pair around every sweep (measurement of
+ * the paper's time-per-gate figures, App. B Table I, on this device).  For
+ * i < min(cap, sweeps): op_ms[i] = duration of sweep i, op_kind[i] its
+ * SV_SWEEP_* kind, op_bytes[i] its algorithmic bytes (host arrays, any may
+ * be NULL); *nops = number of sweeps.  Synchronises. */
+sv_status sv_apply_circuit_timed(sv_state *st, const sv_circuit *c, const sv_opts *opts, int64_t cap,
+                                 float *op_ms, int32_t *op_kind, double *op_bytes, int64_t *nops);
+
+/* p(x) = re^2 + im^2 for x in [begin, begin + count), written to dev_out
+ * (device) as double (out_f64 = 1) or float.  For SV_C64 the two products
+ * are exact in double.  SV_ERANGE if the range leaves [0, 2^n). */
+sv_status sv_probs(sv_state *st, uint64_t begin, uint64_t count, int out_f64, void *dev_out);
+
+/* Output statistics of the current state (one FP64 pass, compensated,
+ * deterministic).  Synchronises. */
+sv_status sv_moments(sv_state *st, sv_stats *out);
+
+/* Draw k bit-strings from p(x) = |<x|psi>|^2 (Sec. II, the sample S).
+ * Exactly reproducible inverse-transform sampling on an integer CDF:
+ * w_x = floor(p(x) 2^62), C_x = w_0 + ... + w_x, W = C_{2^n - 1};
+ * r_i = SplitMix64(seed + (i+1) * 0x9E3779B97F4A7C15);
+ * t_i = floor(r_i W / 2^64); x_i = min{x : C_x > t_i}.
+ * out has k entries, in host memory (out_on_device = 0) or device memory.
+ * k in 0..2^31.  Synchronises. */
+sv_status sv_sample(sv_state *st, int64_t k, uint64_t seed, uint64_t *out, int out_on_device);
+
+/* The same sampler on an explicit distribution: probs (device, N doubles,
+ * need not sum to 1), r64 (device, k random words), out (device, k).
+ * N in 1..2^35.  Uses a scratch allocation of the library.  Synchronises. */
+sv_status sv_sample_from(const double *probs, uint64_t N, const uint64_t *r64,
+                         int64_t k, uint64_t *out, void *hip_stream);
+
+/* Sample cross entropy of Eqs. (ae) and (5):
+ *   ce = ln S - (1/k) sum_i ln p(x_i),  delta_h = ln 2^n + gamma - ce
+ * over k samples (host array); S = sum_x p(x).  ce = +inf when some
+ * p(x_i) = 0; *zero_samples (may be NULL) gets their number.  Synchronises. */
+sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k,
+                           double *ce, double *delta_h, int64_t *zero_samples);
+
+/* Gradient of L(theta) = -(1/k) sum_i ln p_theta(x_i) with respect to
+ * theta (length c->nparams, host), by the adjoint method: the forward state
+ * is rebuilt by applying the inverse gates (no stored history), with a
+ * single-precision copy of the forward state kept at the end of every
+ * checkpoint_c-th cycle (0 = none) and reloaded on the way back.  On entry
+ * the handle may hold anything; on return it holds U(theta)|0>.  loss gets
+ * L(theta).  SV_EINVAL if a parametrised gate is not a rotation. */
+sv_status sv_backward(sv_state *st, const sv_circuit *c, const sv_opts *opts,
+                      const uint64_t *samples, int64_t k, int checkpoint_c,
+                      double *loss, double *grad);
+
+/* Ensemble: simulate count independent circuits from |0...0>, each into its
+ * own handle sts[i] (sizes may differ), in one persistent kernel launch
+ * captured in a HIP graph and replayed, then write each instance's
+ * statistics to out[i].  All handles must share one dtype and stream.
+ * Synchronises. */
+sv_status sv_apply_batch(sv_state **sts, const sv_circuit *cs, int64_t count,
+                         const sv_opts *opts, sv_stats *out);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *sv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SV_ABI_H_INCLUDED */

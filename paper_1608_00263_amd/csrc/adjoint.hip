@@ -1,0 +1,376 @@
+// Adjoint gradient of the sample cross entropy with respect to per-gate
+// rotation offsets.
+//
+// L(theta) = -(1/m) sum_i ln p_theta(x_i).  With psi = U_G ... U_1 |0>,
+// lambda_x = n_x psi_x / (m p_x) and dU_g = D_g U_g, walking the gates
+// backwards from phi = psi, mu = lambda gives
+//     dL/dtheta_g = -2 Re <mu| D_g |phi>,   then phi <- U_g^dag phi, mu <- U_g^dag mu.
+// phi is rebuilt by applying inverse gates rather than stored; a
+// complex64 copy of the forward state at every checkpoint bounds the
+// drift of that uncomputation.
+//
+// The backward sweeps reuse the register tiles of the forward plan with
+// the programs reversed and conjugated, carrying phi and mu through the
+// same tile (so each sweep moves 2 states).  At a parametrised gate the
+// wavefront forms its share of Re <mu| D |phi> before applying the
+// inverse; the shares are written per (tile, slot) and summed in tile
+// order afterwards.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace svi {
+
+template <typename T>
+__device__ __forceinline__ double re_conj_mul(cplx<T> mu, cplx<T> v) {
+    return (double)mu.re * (double)v.re + (double)mu.im * (double)v.im;
+}
+
+template <typename T>
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// sum over this lane's registers of Re conj(mu) (D phi), D on register slot S
+template <typename T, int NR, int S>
+__device__ __forceinline__ double grad_reg(const cplx<T> (&phi)[NR], const cplx<T> (&mu)[NR],
+                                           const Mat2<T> &d) {
+    double acc = 0;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        if (r & (1 << S)) continue;
+        const int r1 = r | (1 << S);
+        cplx<T> d0 = cmad(d.m[1], phi[r1], cmul(d.m[0], phi[r]));
+        cplx<T> d1 = cmad(d.m[3], phi[r1], cmul(d.m[2], phi[r]));
+        acc += re_conj_mul(mu[r], d0) + re_conj_mul(mu[r1], d1);
+    }
+    return acc;
+}
+
+template <typename T, int NR>
+__device__ __forceinline__ double grad_reg_dispatch(const cplx<T> (&phi)[NR], const cplx<T> (&mu)[NR],
+                                                    const Mat2<T> &d, int s) {
+    switch (s) {
+    case 0: return grad_reg<T, NR, 0>(phi, mu, d);
+    case 1: if constexpr (NR > 2) return grad_reg<T, NR, 1>(phi, mu, d); break;
+    case 2: if constexpr (NR > 4) return grad_reg<T, NR, 2>(phi, mu, d); break;
+    case 3: if constexpr (NR > 8) return grad_reg<T, NR, 3>(phi, mu, d); break;
+    case 4: if constexpr (NR > 16) return grad_reg<T, NR, 4>(phi, mu, d); break;
+    default: break;
+    }
+    return 0.0;
+}
+
+template <typename T, int NR, int B>
+__device__ __forceinline__ double grad_lane(const cplx<T> (&phi)[NR], const cplx<T> (&mu)[NR],
+                                            const Mat2<T> &d, int lane) {
+    const bool hi = (lane >> B) & 1;
+    cplx<T> cs = hi ? d.m[3] : d.m[0];
+    cplx<T> cp = hi ? d.m[2] : d.m[1];
+    double acc = 0;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        cplx<T> p;
+        p.re = lane_xor(phi[r].re, 1 << B);
+        p.im = lane_xor(phi[r].im, 1 << B);
+        acc += re_conj_mul(mu[r], cmad(cp, p, cmul(cs, phi[r])));
+    }
+    return acc;
+}
+
+template <typename T, int NR>
+__device__ __forceinline__ double grad_lane_dispatch(const cplx<T> (&phi)[NR], const cplx<T> (&mu)[NR],
+                                                     const Mat2<T> &d, int b, int lane) {
+    switch (b) {
+    case 0: return grad_lane<T, NR, 0>(phi, mu, d, lane);
+    case 1: return grad_lane<T, NR, 1>(phi, mu, d, lane);
+    case 2: return grad_lane<T, NR, 2>(phi, mu, d, lane);
+    case 3: return grad_lane<T, NR, 3>(phi, mu, d, lane);
+    case 4: return grad_lane<T, NR, 4>(phi, mu, d, lane);
+    default: return grad_lane<T, NR, 5>(phi, mu, d, lane);
+    }
+}
+
+template <typename T, int VB>
+__global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi_g, cplx<T> *__restrict__ mu_g,
+                                                       const uint8_t *__restrict__ prog, uint64_t ntiles,
+                                                       double *__restrict__ gpart, int nslots) {
+    constexpr int NR = 1 << VB;
+    const RTHeader *h = reinterpret_cast<const RTHeader *>(prog);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t tile = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
+    if (tile >= ntiles) return;
+    int rq[VB];
+#pragma unroll
+    for (int i = 0; i < VB; i++) rq[i] = h->rq[i];
+    uint64_t base = tile << LANE_BITS;
+#pragma unroll
+    for (int i = 0; i < VB; i++) base = insert_zero(base, rq[i]);
+    uint64_t bq[VB];
+#pragma unroll
+    for (int i = 0; i < VB; i++) bq[i] = 1ull << rq[i];
+    cplx<T> phi[NR], mu[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        phi[r] = phi_g[base + reg_offset<VB>(bq, r) + lane];
+        mu[r] = mu_g[base + reg_offset<VB>(bq, r) + lane];
+    }
+    const RTOp *ops = reinterpret_cast<const RTOp *>(prog + h->op_off);
+    const DiagTerm *terms = reinterpret_cast<const DiagTerm *>(prog + h->term_off);
+    const int nops = h->nops;
+    for (int o = 0; o < nops; o++) {
+        const int kind = ops[o].kind;
+        const int arg = ops[o].a;
+        const int slot = ops[o].slot;
+        if (kind == RT_REG || kind == RT_LANE) {
+            if (slot >= 0) {
+                const Mat2<T> d = load_mat<T>(ops[o].d);
+                double g = kind == RT_REG ? grad_reg_dispatch<T, NR>(phi, mu, d, arg)
+                                          : grad_lane_dispatch<T, NR>(phi, mu, d, arg, lane);
+                g = wave_sum_d<T>(g);
+                if (lane == 0) gpart[tile * (uint64_t)nslots + slot] = g;
+            }
+            const Mat2<T> u = load_mat<T>(ops[o].u);
+            if (kind == RT_REG) {
+                reg_gate_dispatch<T, NR>(phi, u, arg);
+                reg_gate_dispatch<T, NR>(mu, u, arg);
+            } else {
+                lane_gate_dispatch<T, NR>(phi, u, arg, lane);
+                lane_gate_dispatch<T, NR>(mu, u, arg, lane);
+            }
+        } else if (kind == RT_SIGNS) {
+            uint64_t par = 0;
+            const int nt = ops[o].nterms;
+            for (int t = arg; t < arg + nt; t++) {
+                const uint64_t out = terms[t].outside;
+                if ((base & out) != out) continue;
+                const uint32_t lm = terms[t].lanemask;
+                par ^= ((uint32_t)lane & lm) == lm ? terms[t].regset : 0ull;
+            }
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                if ((par >> r) & 1) {
+                    phi[r].re = -phi[r].re; phi[r].im = -phi[r].im;
+                    mu[r].re = -mu[r].re; mu[r].im = -mu[r].im;
+                }
+            }
+        } else if (kind == RT_PHASE) {
+            const uint64_t out = terms[arg].outside;
+            const bool tile_on = (base & out) == out;
+            const uint32_t lm = terms[arg].lanemask;
+            const uint64_t rs = (tile_on && ((uint32_t)lane & lm) == lm) ? terms[arg].regset : 0ull;
+            if (slot >= 0) {
+                cplx<T> dv;
+                dv.re = (T)ops[o].d[6];
+                dv.im = (T)ops[o].d[7];
+                double g = 0;
+#pragma unroll
+                for (int r = 0; r < NR; r++)
+                    if ((rs >> r) & 1) g += re_conj_mul(mu[r], cmul(dv, phi[r]));
+                g = wave_sum_d<T>(g);
+                if (lane == 0) gpart[tile * (uint64_t)nslots + slot] = g;
+            }
+            cplx<T> v;
+            v.re = (T)terms[arg].val[0];
+            v.im = (T)terms[arg].val[1];
+#pragma unroll
+            for (int r = 0; r < NR; r++)
+                if ((rs >> r) & 1) {
+                    phi[r] = cmul(v, phi[r]);
+                    mu[r] = cmul(v, mu[r]);
+                }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        phi_g[base + reg_offset<VB>(bq, r) + lane] = phi[r];
+        mu_g[base + reg_offset<VB>(bq, r) + lane] = mu[r];
+    }
+}
+
+// mu = 0, then mu_x += psi_x / (m p_x) for every sample x (repeated samples
+// add identical terms, so the sum does not depend on their order)
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_lambda(const cplx<T> *__restrict__ psi, cplx<T> *__restrict__ mu,
+                                                  const uint64_t *__restrict__ x, int64_t m, uint64_t mask) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= m) return;
+    const uint64_t xi = x[i] & mask;
+    const cplx<T> a = psi[xi];
+    const double p = (double)a.re * (double)a.re + (double)a.im * (double)a.im;
+    const double s = 1.0 / ((double)m * p);
+    atomicAdd(&mu[xi].re, (T)(s * (double)a.re));
+    atomicAdd(&mu[xi].im, (T)(s * (double)a.im));
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_zero(cplx<T> *__restrict__ v, uint64_t N) {
+    uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < N; i += stride) {
+        cplx<T> z;
+        z.re = 0;
+        z.im = 0;
+        v[i] = z;
+    }
+}
+
+template <typename A, typename B>
+__global__ __launch_bounds__(BLOCK) void k_convert(const cplx<A> *__restrict__ src, cplx<B> *__restrict__ dst,
+                                                   uint64_t N) {
+    uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < N; i += stride) {
+        cplx<B> o;
+        o.re = (B)src[i].re;
+        o.im = (B)src[i].im;
+        dst[i] = o;
+    }
+}
+
+// gradient slot s = -2 sum over tiles of gpart[tile][s], tiles in order
+// (Neumaier)
+__global__ void k_grad_reduce(const double *__restrict__ gpart, uint64_t ntiles, int nslots,
+                              double *__restrict__ out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslots) return;
+    double sum = 0, c = 0;
+    for (uint64_t t = 0; t < ntiles; t++) {
+        const double x = gpart[t * (uint64_t)nslots + s];
+        const double u = sum + x;
+        if (fabs(sum) >= fabs(x)) c += (sum - u) + x;
+        else c += (x - u) + sum;
+        sum = u;
+    }
+    out[s] = -2.0 * (sum + c);
+}
+
+static unsigned ggrid(uint64_t items) {
+    uint64_t g = (items + BLOCK - 1) / BLOCK;
+    const uint64_t cap = 256ull * 64;
+    return (unsigned)(g < cap ? (g ? g : 1) : cap);
+}
+
+template <typename T>
+static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *samples, int64_t k,
+                                double *loss, double *grad, int nparams) {
+    const int n = st->n;
+    const uint64_t N = 1ull << n;
+    hipStream_t s = st->stream;
+    const int nslots = (int)plan.slot_param.size();
+    // device scratch: mu | checkpoints (complex64) | samples | gradient partials | slot sums
+    int vb = 0;
+    for (const Op &op : plan.bops)
+        if (op.type == OP_ADJ_REGTILE) vb = op.vbits;
+    const uint64_t ntiles = vb ? N >> (LANE_BITS + vb) : 0;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_mu = al(N * sizeof(cplx<T>));
+    const size_t b_ck = al(N * sizeof(cplx<float>)) * (size_t)plan.ncheckpoints;
+    const size_t b_x = al((size_t)k * 8);
+    const size_t b_gp = al((size_t)ntiles * (nslots ? nslots : 1) * 8);
+    const size_t b_gs = al((size_t)(nslots ? nslots : 1) * 8);
+    SV_TRY(st->ws2.reserve(b_mu + b_ck + b_x + b_gp + b_gs));
+    uint8_t *w = (uint8_t *)st->ws2.ptr;
+    cplx<T> *mu = (cplx<T> *)w;
+    uint8_t *ck = w + b_mu;
+    uint64_t *dx = (uint64_t *)(ck + b_ck);
+    double *gpart = (double *)((uint8_t *)dx + b_x);
+    double *gsum = (double *)((uint8_t *)gpart + b_gp);
+    cplx<T> *phi = (cplx<T> *)st->data;
+    auto ckpt = [&](int i) { return (cplx<float> *)(ck + (size_t)i * al(N * sizeof(cplx<float>))); };
+
+    // forward pass from |0..0>, storing checkpoints
+    for (const Op &op : plan.ops) {
+        if (op.type == OP_CKPT_STORE) {
+            if (sizeof(T) == 4)
+                SV_HIP(hipMemcpyAsync(ckpt(op.q0), phi, N * sizeof(cplx<float>), hipMemcpyDeviceToDevice, s));
+            else
+                hipLaunchKernelGGL((k_convert<T, float>), dim3(ggrid(N)), dim3(BLOCK), 0, s, phi, ckpt(op.q0), N);
+        } else {
+            SV_TRY(launch_op(st, plan, op, phi));
+        }
+    }
+    st->known_zero = false;
+    // loss and lambda
+    SV_HIP(hipMemcpyAsync(dx, samples, (size_t)k * 8, hipMemcpyHostToDevice, s));
+    double sum_log = 0;
+    int64_t zeros = 0;
+    SV_TRY(run_cross_entropy(st, phi, dx, k, 1.0, &sum_log, &zeros));
+    if (zeros) return fail(SV_ESTATE, "sv_backward: a sample has probability 0");
+    *loss = -sum_log / (double)k;
+    hipLaunchKernelGGL(k_zero<T>, dim3(ggrid(N)), dim3(BLOCK), 0, s, mu, N);
+    hipLaunchKernelGGL(k_lambda<T>, dim3((unsigned)((k + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, phi, mu,
+                       dx, k, N - 1);
+    SV_HIP(hipGetLastError());
+    // backward sweeps
+    for (const Op &op : plan.bops) {
+        if (op.type == OP_CKPT_LOAD) {
+            if (sizeof(T) == 4)
+                SV_HIP(hipMemcpyAsync(phi, ckpt(op.q0), N * sizeof(cplx<float>), hipMemcpyDeviceToDevice, s));
+            else
+                hipLaunchKernelGGL((k_convert<float, T>), dim3(ggrid(N)), dim3(BLOCK), 0, s, ckpt(op.q0), phi, N);
+            continue;
+        }
+        const uint8_t *prog = (const uint8_t *)plan.dprog + op.prog_off;
+        const unsigned grid = (unsigned)((ntiles + 3) / 4);
+#define ADJ_CASE(VB)                                                                                     \
+    case VB:                                                                                             \
+        hipLaunchKernelGGL((k_regtile_adj<T, VB>), dim3(grid), dim3(BLOCK), 0, s, phi, mu, prog, ntiles, \
+                           gpart, nslots);                                                               \
+        break;
+        switch (op.vbits) {
+            ADJ_CASE(1) ADJ_CASE(2) ADJ_CASE(3) ADJ_CASE(4) ADJ_CASE(5)
+        default: return fail(SV_EINVAL, "adjoint tile width out of range");
+        }
+#undef ADJ_CASE
+        SV_HIP(hipGetLastError());
+    }
+    std::vector<double> slots(nslots);
+    if (nslots) {
+        hipLaunchKernelGGL(k_grad_reduce, dim3((nslots + 255) / 256), dim3(256), 0, s, gpart, ntiles, nslots,
+                           gsum);
+        SV_HIP(hipGetLastError());
+        SV_HIP(hipMemcpyAsync(slots.data(), gsum, nslots * 8, hipMemcpyDeviceToHost, s));
+    }
+    SV_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < nparams; i++) grad[i] = 0.0;
+    for (int i = 0; i < nslots; i++) grad[plan.slot_param[i]] += slots[i];
+    return SV_OK;
+}
+
+}  // namespace svi
+
+using namespace svi;
+
+extern "C" sv_status sv_backward(sv_state *st, const sv_circuit *c, const sv_opts *opts, const uint64_t *samples,
+                                 int64_t k, int checkpoint_c, double *loss, double *grad) {
+    if (!st || !st->data) return fail(SV_EINVAL, "null state");
+    if (!c || c->n != st->n) return fail(SV_EINVAL, "circuit qubit count differs from the state's");
+    if (k <= 0 || !samples || !loss || (c->nparams > 0 && !grad))
+        return fail(SV_EINVAL, "need samples, a loss and a gradient buffer");
+    if (checkpoint_c < 0) return fail(SV_EINVAL, "checkpoint interval must be >= 0");
+    PlanRequest rq{};
+    rq.n = st->n;
+    rq.dtype = st->dt;
+    rq.mode = SV_MODE_REGTILE;
+    rq.tile = opts ? opts->tile_qubits : 0;
+    rq.from_zero = true;
+    rq.k_max = 1000 + checkpoint_c;   // distinct cache key per checkpoint interval
+    std::string key = "adj:" + plan_key(c, rq);
+    std::shared_ptr<Plan> plan;
+    auto it = st->plans.find(key);
+    if (it != st->plans.end()) {
+        plan = it->second;
+    } else {
+        plan = std::make_shared<Plan>();
+        SV_TRY(build_adjoint_plan(c, rq, checkpoint_c, plan.get()));
+        SV_TRY(upload_plan(st, plan.get()));
+        st->plans[key] = plan;
+    }
+    if (st->dt == SV_C64) return backward_typed<float>(st, *plan, samples, k, loss, grad, c->nparams);
+    return backward_typed<double>(st, *plan, samples, k, loss, grad, c->nparams);
+}

@@ -1,0 +1,332 @@
+// C ABI entry points (include/sv.h): handle management, argument checks,
+// plan cache and dispatch.  All device work is enqueued on the handle's
+// stream; functions returning host scalars synchronise it.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <new>
+
+#include "internal.h"
+
+namespace svi {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+sv_status fail(sv_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+sv_status hip_fail(hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    g_err = m;
+    return e == hipErrorOutOfMemory ? SV_ENOMEM : SV_EDEVICE;
+}
+
+sv_status Workspace::reserve(size_t need) {
+    if (need <= bytes) return SV_OK;
+    if (ptr) {
+        SV_HIP(hipDeviceSynchronize());
+        SV_HIP(hipFree(ptr));
+        ptr = nullptr;
+        bytes = 0;
+    }
+    size_t want = need < ((size_t)1 << 20) ? ((size_t)1 << 20) : need;
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        return hip_fail(e, "workspace hipMalloc");
+    }
+    bytes = want;
+    return SV_OK;
+}
+
+Workspace::~Workspace() {
+    if (ptr) (void)hipFree(ptr);
+}
+
+static int max_qubits(sv_dtype dt) { return dt == SV_C64 ? 35 : 34; }
+
+static sv_status check_state(sv_state *st) {
+    if (!st) return fail(SV_EINVAL, "null state handle");
+    if (!st->data) return fail(SV_ESTATE, "state has no device buffer");
+    return SV_OK;
+}
+
+static sv_status check_circuit(sv_state *st, const sv_circuit *c) {
+    if (!c) return fail(SV_EINVAL, "null circuit");
+    if (c->n != st->n) return fail(SV_EINVAL, "circuit qubit count differs from the state's");
+    if (c->ngates < 0 || (c->ngates > 0 && !c->gates)) return fail(SV_EINVAL, "bad gate array");
+    if (c->nparams < 0 || (c->nparams > 0 && !c->theta)) return fail(SV_EINVAL, "bad theta array");
+    if (c->nmats < 0 || (c->nmats > 0 && !c->mats)) return fail(SV_EINVAL, "bad matrix array");
+    return SV_OK;
+}
+
+static PlanRequest make_request(sv_state *st, const sv_opts *o) {
+    PlanRequest rq{};
+    rq.n = st->n;
+    rq.dtype = st->dt;
+    rq.mode = o ? o->mode : SV_MODE_AUTO;
+    rq.k_max = o ? o->k_max : 0;
+    rq.tile = o ? o->tile_qubits : 0;
+    rq.force_zero = o && (o->flags & SV_FLAG_FROM_ZERO);
+    rq.from_zero = st->known_zero || rq.force_zero;
+    return rq;
+}
+
+sv_status get_plan(sv_state *st, const sv_circuit *c, PlanRequest rq, std::shared_ptr<Plan> *out) {
+    if (rq.mode == SV_MODE_AUTO) rq.mode = SV_MODE_REGTILE;
+    if (rq.mode < SV_MODE_PLAIN || rq.mode > SV_MODE_REGTILE) return fail(SV_EINVAL, "unknown mode");
+    if (rq.k_max < 0 || rq.k_max > 5) return fail(SV_EINVAL, "k_max must be 0..5");
+    std::string key = plan_key(c, rq);
+    auto it = st->plans.find(key);
+    if (it != st->plans.end()) {
+        *out = it->second;
+        return SV_OK;
+    }
+    auto plan = std::make_shared<Plan>();
+    SV_TRY(build_plan(c, rq, plan.get()));
+    SV_TRY(upload_plan(st, plan.get()));
+    if (st->plans.size() > 64) st->plans.clear();
+    st->plans[key] = plan;
+    *out = plan;
+    return SV_OK;
+}
+
+sv_status run_plan(sv_state *st, const Plan &plan) {
+    for (const Op &op : plan.ops) SV_TRY(launch_op(st, plan, op, st->data));
+    st->known_zero = false;
+    return SV_OK;
+}
+
+}  // namespace svi
+
+using namespace svi;
+
+extern "C" {
+
+const char *sv_last_error(void) { return g_err.c_str(); }
+
+static sv_status new_state(int n, sv_dtype dt, void *stream, sv_state **out) {
+    if (!out) return fail(SV_EINVAL, "null output handle");
+    *out = nullptr;
+    if (dt != SV_C64 && dt != SV_C128) return fail(SV_EINVAL, "unknown dtype");
+    if (n < 1 || n > max_qubits(dt)) {
+        char b[96];
+        snprintf(b, sizeof b, "n = %d out of range 1..%d", n, max_qubits(dt));
+        return fail(SV_ERANGE, b);
+    }
+    sv_state *st = new (std::nothrow) sv_state();
+    if (!st) return fail(SV_ENOMEM, "host allocation failed");
+    st->n = n;
+    st->dt = dt;
+    st->stream = (hipStream_t)stream;
+    hipError_t e = hipGetDevice(&st->device);
+    if (e != hipSuccess) {
+        delete st;
+        return hip_fail(e, "hipGetDevice");
+    }
+    *out = st;
+    return SV_OK;
+}
+
+sv_status sv_alloc(int n, sv_dtype dt, void *hip_stream, sv_state **out) {
+    sv_state *st = nullptr;
+    SV_TRY(new_state(n, dt, hip_stream, &st));
+    size_t bytes = (size_t)state_bytes(n, dt);
+    size_t freeb = 0, total = 0;
+    hipError_t e = hipMemGetInfo(&freeb, &total);
+    if (e != hipSuccess) {
+        delete st;
+        return hip_fail(e, "hipMemGetInfo");
+    }
+    if (bytes > freeb) {
+        delete st;
+        char b[128];
+        snprintf(b, sizeof b, "state needs %zu bytes, %zu free", bytes, freeb);
+        return fail(SV_ENOMEM, b);
+    }
+    e = hipMalloc(&st->data, bytes);
+    if (e != hipSuccess) {
+        delete st;
+        return hip_fail(e, "hipMalloc(state)");
+    }
+    st->owned = true;
+    sv_status rc = sv_reset(st);
+    if (rc != SV_OK) {
+        sv_free(st);
+        return rc;
+    }
+    *out = st;
+    return SV_OK;
+}
+
+sv_status sv_attach(int n, sv_dtype dt, void *dev_ptr, void *hip_stream, sv_state **out) {
+    if (!dev_ptr) return fail(SV_EINVAL, "null device pointer");
+    sv_state *st = nullptr;
+    SV_TRY(new_state(n, dt, hip_stream, &st));
+    st->data = dev_ptr;
+    st->owned = false;
+    *out = st;
+    return SV_OK;
+}
+
+sv_status sv_free(sv_state *st) {
+    if (!st) return SV_OK;
+    if (st->stream) (void)hipStreamSynchronize(st->stream);
+    else (void)hipDeviceSynchronize();
+    if (st->owned && st->data) (void)hipFree(st->data);
+    delete st;
+    return SV_OK;
+}
+
+sv_status sv_reset(sv_state *st) {
+    SV_TRY(check_state(st));
+    SV_TRY(launch_init_zero(st, st->data));
+    st->known_zero = true;
+    return SV_OK;
+}
+
+sv_status sv_data(sv_state *st, void **dev_ptr) {
+    SV_TRY(check_state(st));
+    if (!dev_ptr) return fail(SV_EINVAL, "null output pointer");
+    *dev_ptr = st->data;
+    st->known_zero = false;   // the caller may write through the pointer
+    return SV_OK;
+}
+
+sv_status sv_apply_circuit(sv_state *st, const sv_circuit *c, const sv_opts *opts) {
+    SV_TRY(check_state(st));
+    SV_TRY(check_circuit(st, c));
+    std::shared_ptr<Plan> plan;
+    SV_TRY(get_plan(st, c, make_request(st, opts), &plan));
+    return run_plan(st, *plan);
+}
+
+static int32_t sweep_kind(const Op &op) {
+    switch (op.type) {
+    case OP_INIT_UNIFORM: case OP_INIT_ZERO: return SV_SWEEP_INIT;
+    case OP_PLAIN_1Q: return SV_SWEEP_PLAIN_1Q;
+    case OP_PLAIN_CZ: return SV_SWEEP_PLAIN_CZ;
+    case OP_SPEC_DENSE: return SV_SWEEP_SPEC_DENSE;
+    case OP_SPEC_REAL: return SV_SWEEP_SPEC_REAL;
+    case OP_SPEC_DIAG: return SV_SWEEP_SPEC_DIAG;
+    case OP_SPEC_CZ: return SV_SWEEP_SPEC_CZ;
+    case OP_REGTILE: return SV_SWEEP_REGTILE;
+    case OP_LDSTILE: return op.mfma ? SV_SWEEP_LDSTILE_MFMA : SV_SWEEP_LDSTILE;
+    default: return 0;
+    }
+}
+
+sv_status sv_apply_circuit_timed(sv_state *st, const sv_circuit *c, const sv_opts *opts, int64_t cap,
+                                 float *op_ms, int32_t *op_kind, double *op_bytes, int64_t *nops) {
+    SV_TRY(check_state(st));
+    SV_TRY(check_circuit(st, c));
+    std::shared_ptr<Plan> plan;
+    SV_TRY(get_plan(st, c, make_request(st, opts), &plan));
+    const size_t m = plan->ops.size();
+    std::vector<hipEvent_t> ev(m + 1);
+    for (auto &e : ev) SV_HIP(hipEventCreate(&e));
+    sv_status rc = SV_OK;
+    hipError_t he = hipEventRecord(ev[0], st->stream);
+    if (he != hipSuccess) rc = hip_fail(he, "hipEventRecord");
+    for (size_t i = 0; rc == SV_OK && i < m; i++) {
+        rc = launch_op(st, *plan, plan->ops[i], st->data);
+        if (rc == SV_OK) {
+            he = hipEventRecord(ev[i + 1], st->stream);
+            if (he != hipSuccess) rc = hip_fail(he, "hipEventRecord");
+        }
+    }
+    if (rc == SV_OK) {
+        he = hipEventSynchronize(ev[m]);
+        if (he != hipSuccess) rc = hip_fail(he, "hipEventSynchronize");
+    }
+    for (size_t i = 0; rc == SV_OK && i < m && (int64_t)i < cap; i++) {
+        float ms = 0;
+        he = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        if (he != hipSuccess) { rc = hip_fail(he, "hipEventElapsedTime"); break; }
+        if (op_ms) op_ms[i] = ms;
+        if (op_kind) op_kind[i] = sweep_kind(plan->ops[i]);
+        if (op_bytes) op_bytes[i] = plan->ops[i].bytes;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (rc != SV_OK) return rc;
+    st->known_zero = false;
+    if (nops) *nops = (int64_t)m;
+    return SV_OK;
+}
+
+sv_status sv_plan_info(sv_state *st, const sv_circuit *c, const sv_opts *opts, int64_t *sweeps,
+                       double *bytes) {
+    SV_TRY(check_state(st));
+    SV_TRY(check_circuit(st, c));
+    std::shared_ptr<Plan> plan;
+    SV_TRY(get_plan(st, c, make_request(st, opts), &plan));
+    if (sweeps) *sweeps = plan->sweeps;
+    if (bytes) *bytes = plan->bytes;
+    return SV_OK;
+}
+
+sv_status sv_probs(sv_state *st, uint64_t begin, uint64_t count, int out_f64, void *dev_out) {
+    SV_TRY(check_state(st));
+    const uint64_t N = 1ull << st->n;
+    if (begin > N || count > N - begin) return fail(SV_ERANGE, "probability range outside the state");
+    if (count && !dev_out) return fail(SV_EINVAL, "null output buffer");
+    return run_probs(st, begin, count, out_f64, dev_out);
+}
+
+sv_status sv_moments(sv_state *st, sv_stats *out) {
+    SV_TRY(check_state(st));
+    if (!out) return fail(SV_EINVAL, "null output");
+    return run_stats(st, st->data, out);
+}
+
+sv_status sv_sample(sv_state *st, int64_t k, uint64_t seed, uint64_t *out, int out_on_device) {
+    SV_TRY(check_state(st));
+    if (k < 0 || k > ((int64_t)1 << 31)) return fail(SV_ERANGE, "sample count out of range");
+    if (k == 0) return SV_OK;
+    if (!out) return fail(SV_EINVAL, "null output");
+    uint64_t *dout = out;
+    if (!out_on_device) {
+        SV_TRY(st->ws2.reserve((size_t)k * 8));
+        dout = (uint64_t *)st->ws2.ptr;
+    }
+    SV_TRY(run_sample(st, st->data, k, seed, dout));
+    if (!out_on_device)
+        SV_HIP(hipMemcpyAsync(out, dout, (size_t)k * 8, hipMemcpyDeviceToHost, st->stream));
+    SV_HIP(hipStreamSynchronize(st->stream));
+    return SV_OK;
+}
+
+sv_status sv_sample_from(const double *probs, uint64_t N, const uint64_t *r64, int64_t k, uint64_t *out,
+                         void *hip_stream) {
+    if (!probs || !r64 || (k > 0 && !out)) return fail(SV_EINVAL, "null pointer");
+    if (N < 1 || N > (1ull << 35)) return fail(SV_ERANGE, "N out of range");
+    if (k < 0 || k > ((int64_t)1 << 31)) return fail(SV_ERANGE, "sample count out of range");
+    return run_sample_from(probs, N, r64, k, out, (hipStream_t)hip_stream);
+}
+
+sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k, double *ce, double *delta_h,
+                           int64_t *zero_samples) {
+    SV_TRY(check_state(st));
+    if (k <= 0 || !samples || !ce) return fail(SV_EINVAL, "need k > 0 samples and an output");
+    double S = 0;
+    SV_TRY(run_norm(st, st->data, &S));
+    SV_TRY(st->ws2.reserve((size_t)k * 8));
+    uint64_t *dx = (uint64_t *)st->ws2.ptr;
+    SV_HIP(hipMemcpyAsync(dx, samples, (size_t)k * 8, hipMemcpyHostToDevice, st->stream));
+    double sum_log = 0;
+    int64_t zeros = 0;
+    SV_TRY(run_cross_entropy(st, st->data, dx, k, S, &sum_log, &zeros));
+    const double euler_gamma = 0.57721566490153286061;
+    *ce = zeros ? INFINITY : std::log(S) - sum_log / (double)k;
+    if (delta_h) *delta_h = std::log(std::ldexp(1.0, st->n)) + euler_gamma - *ce;
+    if (zero_samples) *zero_samples = zeros;
+    return SV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,242 @@
+// Host replay of sweep plans (include/sv_host.h): interprets the tile
+// programs byte for byte as the GPU kernels do, in double precision.
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "../../include/sv_host.h"
+#include "internal.h"
+
+namespace svi {
+
+using cx = std::complex<double>;
+
+static uint64_t ins0(uint64_t x, int q) {
+    return ((x >> q) << (q + 1)) | (x & ((1ull << q) - 1));
+}
+
+static cx to_cx(const double *u, int i) { return cx(u[2 * i], u[2 * i + 1]); }
+
+static void emulate_regtile(const Plan &plan, const Op &op, int n, cx *psi) {
+    const uint8_t *prog = plan.prog.data() + op.prog_off;
+    const RTHeader *h = (const RTHeader *)prog;
+    const RTOp *ops = (const RTOp *)(prog + h->op_off);
+    const DiagTerm *terms = (const DiagTerm *)(prog + h->term_off);
+    const int vb = op.vbits, nr = 1 << vb;
+    const uint64_t ntiles = (1ull << n) >> (LANE_BITS + vb);
+    std::vector<uint64_t> roff(nr, 0);
+    for (int r = 1; r < nr; r++) roff[r] = roff[r & (r - 1)] | (1ull << h->rq[__builtin_ctz(r)]);
+    std::vector<cx> a(64 * nr);
+    const bool f32 = plan.dtype == SV_C64;
+    auto rnd = [&](cx v) { return f32 ? cx((float)v.real(), (float)v.imag()) : v; };
+    for (uint64_t tile = 0; tile < ntiles; tile++) {
+        uint64_t base = tile << LANE_BITS;
+        for (int i = 0; i < vb; i++) base = ins0(base, h->rq[i]);
+        for (int l = 0; l < 64; l++)
+            for (int r = 0; r < nr; r++) a[l * nr + r] = psi[base + roff[r] + l];
+        for (int o = 0; o < h->nops; o++) {
+            const RTOp &p = ops[o];
+            cx u[4];
+            for (int i = 0; i < 4; i++) u[i] = rnd(to_cx(p.u, i));
+            if (p.kind == RT_REG) {
+                for (int l = 0; l < 64; l++)
+                    for (int r = 0; r < nr; r++) {
+                        if (r & (1 << p.a)) continue;
+                        cx &x = a[l * nr + r], &y = a[l * nr + (r | (1 << p.a))];
+                        cx nx = u[0] * x + u[1] * y, ny = u[2] * x + u[3] * y;
+                        x = nx;
+                        y = ny;
+                    }
+            } else if (p.kind == RT_LANE) {
+                for (int l = 0; l < 64; l++) {
+                    if (l & (1 << p.a)) continue;
+                    int l1 = l | (1 << p.a);
+                    for (int r = 0; r < nr; r++) {
+                        cx &x = a[l * nr + r], &y = a[l1 * nr + r];
+                        cx nx = u[0] * x + u[1] * y, ny = u[2] * x + u[3] * y;
+                        x = nx;
+                        y = ny;
+                    }
+                }
+            } else if (p.kind == RT_SIGNS || p.kind == RT_PHASE) {
+                int t0 = p.a, t1 = p.a + (p.kind == RT_SIGNS ? p.nterms : 1);
+                for (int l = 0; l < 64; l++) {
+                    uint64_t par = 0;
+                    for (int t = t0; t < t1; t++) {
+                        const DiagTerm &d = terms[t];
+                        if ((base & d.outside) != d.outside) continue;
+                        if (((uint32_t)l & d.lanemask) != d.lanemask) continue;
+                        if (p.kind == RT_SIGNS) {
+                            par ^= d.regset;
+                        } else {
+                            cx v = rnd(cx(d.val[0], d.val[1]));
+                            for (int r = 0; r < nr; r++)
+                                if ((d.regset >> r) & 1) a[l * nr + r] *= v;
+                        }
+                    }
+                    for (int r = 0; r < nr; r++)
+                        if ((par >> r) & 1) a[l * nr + r] = -a[l * nr + r];
+                }
+            }
+        }
+        for (int l = 0; l < 64; l++)
+            for (int r = 0; r < nr; r++) psi[base + roff[r] + l] = a[l * nr + r];
+    }
+}
+
+static void emulate_ldstile(const Plan &plan, const Op &op, int n, cx *psi) {
+    const uint8_t *prog = plan.prog.data() + op.prog_off;
+    const LTHeader *h = (const LTHeader *)prog;
+    const LTOp *ops = (const LTOp *)(prog + h->op_off);
+    const LTTerm *terms = (const LTTerm *)(prog + h->term_off);
+    const int mb = op.vbits, nh = mb - LANE_BITS;
+    const uint32_t tsz = 1u << mb;
+    const uint64_t ntiles = (1ull << n) >> mb;
+    std::vector<uint64_t> goff(tsz);
+    for (uint32_t j = 0; j < tsz; j++) {
+        uint64_t o = j & 63;
+        for (int b = 0; b < nh; b++)
+            if ((j >> (LANE_BITS + b)) & 1) o |= 1ull << h->hq[b];
+        goff[j] = o;
+    }
+    std::vector<cx> lds(tsz);
+    const bool f32 = plan.dtype == SV_C64;
+    for (uint64_t tile = 0; tile < ntiles; tile++) {
+        uint64_t base = tile << LANE_BITS;
+        for (int i = 0; i < nh; i++) base = ins0(base, h->hq[i]);
+        for (uint32_t j = 0; j < tsz; j++) lds[j] = psi[base + goff[j]];
+        for (int o = 0; o < h->nops; o++) {
+            const LTOp &p = ops[o];
+            if (p.kind == LT_BLOCK) {
+                const int k = p.k, d = 1 << k;
+                std::vector<cx> U(d * d);
+                for (int i = 0; i < d * d; i++) {
+                    if (f32) {
+                        const float *f = (const float *)(prog + p.mat_off);
+                        U[i] = cx(f[2 * i], f[2 * i + 1]);
+                    } else {
+                        const double *f = (const double *)(prog + p.mat_off);
+                        U[i] = cx(f[2 * i], f[2 * i + 1]);
+                    }
+                }
+                std::vector<uint32_t> off(d, 0);
+                for (int s = 1; s < d; s++) off[s] = off[s & (s - 1)] | (1u << p.pos[__builtin_ctz(s)]);
+                std::vector<cx> x(d);
+                for (uint32_t c = 0; c < (tsz >> k); c++) {
+                    uint32_t b = c;
+                    for (int j = 0; j < k; j++) b = (uint32_t)ins0(b, p.pos[j]);
+                    for (int s = 0; s < d; s++) x[s] = lds[b + off[s]];
+                    for (int r = 0; r < d; r++) {
+                        cx acc = 0;
+                        for (int s = 0; s < d; s++) acc += U[r * d + s] * x[s];
+                        lds[b + off[r]] = acc;
+                    }
+                }
+            } else {
+                for (uint32_t j = 0; j < tsz; j++) {
+                    uint32_t t = j & 255, it = j >> 8;
+                    for (int q = p.term0; q < p.term0 + p.nterms; q++) {
+                        const LTTerm &tm = terms[q];
+                        if ((base & tm.outside) != tm.outside) continue;
+                        uint32_t lm = tm.localmask & 0xFFu;
+                        if ((t & lm) != lm || !((tm.itset >> it) & 1)) continue;
+                        if (p.kind == LT_SIGNS) lds[j] = -lds[j];
+                        else {
+                            cx v(tm.val[0], tm.val[1]);
+                            if (f32) v = cx((float)v.real(), (float)v.imag());
+                            lds[j] *= v;
+                        }
+                    }
+                }
+            }
+        }
+        for (uint32_t j = 0; j < tsz; j++) psi[base + goff[j]] = lds[j];
+    }
+}
+
+static void emulate_op(const Plan &plan, const Op &op, int n, cx *psi) {
+    const uint64_t N = 1ull << n;
+    const bool f32 = plan.dtype == SV_C64;
+    auto rnd = [&](cd v) { return f32 ? cx((float)v.re, (float)v.im) : cx(v.re, v.im); };
+    switch (op.type) {
+    case OP_INIT_UNIFORM: {
+        double v = std::ldexp(1.0, -n / 2);
+        if (n & 1) v /= std::sqrt(2.0);
+        if (f32) v = (float)v;
+        for (uint64_t i = 0; i < N; i++) psi[i] = v;
+        break;
+    }
+    case OP_INIT_ZERO:
+        for (uint64_t i = 0; i < N; i++) psi[i] = 0;
+        psi[0] = 1;
+        break;
+    case OP_PLAIN_1Q: case OP_SPEC_DENSE: case OP_SPEC_REAL: {
+        cx u[4] = {rnd(op.u.m[0]), rnd(op.u.m[1]), rnd(op.u.m[2]), rnd(op.u.m[3])};
+        for (uint64_t p = 0; p < N / 2; p++) {
+            uint64_t i0 = ins0(p, op.q0), i1 = i0 | (1ull << op.q0);
+            cx a = psi[i0], b = psi[i1];
+            psi[i0] = u[0] * a + u[1] * b;
+            psi[i1] = u[2] * a + u[3] * b;
+        }
+        break;
+    }
+    case OP_PLAIN_CZ: case OP_SPEC_CZ: {
+        uint64_t m = (1ull << op.q0) | (1ull << op.q1);
+        for (uint64_t i = 0; i < N; i++)
+            if ((i & m) == m) psi[i] = -psi[i];
+        break;
+    }
+    case OP_SPEC_DIAG: {
+        cx d = rnd(op.u.m[3]);
+        for (uint64_t i = 0; i < N; i++)
+            if ((i >> op.q0) & 1) psi[i] *= d;
+        break;
+    }
+    case OP_REGTILE: emulate_regtile(plan, op, n, psi); break;
+    case OP_LDSTILE: emulate_ldstile(plan, op, n, psi); break;
+    default: break;   // adjoint-only ops never appear in forward plans
+    }
+}
+
+static sv_status host_plan(const sv_circuit *c, sv_dtype dt, const sv_opts *o, int from_zero, Plan *plan) {
+    if (!c || c->n < 1 || c->n > 35) return fail(SV_EINVAL, "bad circuit");
+    if (c->ngates < 0 || (c->ngates > 0 && !c->gates)) return fail(SV_EINVAL, "bad gate array");
+    PlanRequest rq{};
+    rq.n = c->n;
+    rq.dtype = dt;
+    rq.mode = o ? o->mode : SV_MODE_AUTO;
+    if (rq.mode == SV_MODE_AUTO) rq.mode = SV_MODE_REGTILE;
+    rq.k_max = o ? o->k_max : 0;
+    rq.tile = o ? o->tile_qubits : 0;
+    rq.from_zero = from_zero != 0;
+    rq.force_zero = o && (o->flags & SV_FLAG_FROM_ZERO);
+    return build_plan(c, rq, plan);
+}
+
+}  // namespace svi
+
+using namespace svi;
+
+extern "C" sv_status sv_host_plan(const sv_circuit *c, sv_dtype dt, const sv_opts *opts, int from_zero,
+                                  int64_t *sweeps, double *bytes, int64_t *mfma_sweeps) {
+    Plan plan;
+    SV_TRY(host_plan(c, dt, opts, from_zero, &plan));
+    if (sweeps) *sweeps = plan.sweeps;
+    if (bytes) *bytes = plan.bytes;
+    if (mfma_sweeps) {
+        int64_t m = 0;
+        for (const Op &op : plan.ops) m += op.mfma ? 1 : 0;
+        *mfma_sweeps = m;
+    }
+    return SV_OK;
+}
+
+extern "C" sv_status sv_host_emulate(const sv_circuit *c, sv_dtype dt, const sv_opts *opts, int from_zero,
+                                     double *psi) {
+    if (!psi) return fail(SV_EINVAL, "null state");
+    if (c && c->n > 26) return fail(SV_ERANGE, "host replay limited to 26 qubits");
+    Plan plan;
+    SV_TRY(host_plan(c, dt, opts, from_zero, &plan));
+    for (const Op &op : plan.ops) emulate_op(plan, op, c->n, (cx *)psi);
+    return SV_OK;
+}

@@ -1,0 +1,267 @@
+// Internal declarations shared by the library's translation units (host and
+// device).  Not part of the public ABI (include/sv.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/sv.h"
+
+namespace svi {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+sv_status fail(sv_status st, const std::string &msg);
+sv_status hip_fail(hipError_t e, const char *what);
+
+#define SV_HIP(call)                                                 \
+    do {                                                             \
+        hipError_t e_ = (call);                                      \
+        if (e_ != hipSuccess) return ::svi::hip_fail(e_, #call);     \
+    } while (0)
+
+#define SV_TRY(expr)                                                 \
+    do {                                                             \
+        sv_status s_ = (expr);                                       \
+        if (s_ != SV_OK) return s_;                                  \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// complex helpers (host side, FP64)
+// ---------------------------------------------------------------------------
+struct cd {
+    double re, im;
+};
+inline cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+inline cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+inline cd cconj(cd a) { return {a.re, -a.im}; }
+
+// 2x2 complex matrix, row-major: m[0] m[1] / m[2] m[3]
+struct M2 {
+    cd m[4];
+};
+M2 m2_mul(const M2 &a, const M2 &b);   // a * b
+M2 m2_dag(const M2 &a);
+
+// Gate matrix of a record (kind, rotation offset).  False on a bad kind.
+bool gate_matrix(int kind, double theta, const double *mat8, M2 *out);
+// dU/dtheta = D U for the rotation kinds; false for others.
+bool derivative_generator(int kind, M2 *out);
+
+// ---------------------------------------------------------------------------
+// tile programs (device-readable, 8-byte aligned plain structs)
+// ---------------------------------------------------------------------------
+constexpr int LANE_BITS = 6;          // 64-lane wavefront = qubits 0..5
+
+// register-tile ops
+enum RTKind : int32_t {
+    RT_REG = 1,     // dense 2x2 on register slot a
+    RT_LANE = 2,    // dense 2x2 on lane bit a (cross-lane shuffles)
+    RT_SIGNS = 3,   // nterms sign flips (CZ) starting at term index a
+    RT_PHASE = 4,   // one general diagonal phase term (index a)
+    RT_GRAD = 5,    // adjoint: inner product with a derivative generator
+};
+
+struct RTOp {               // 144 bytes
+    int32_t kind;
+    int32_t a;              // register slot / lane bit / first term
+    int32_t nterms;
+    int32_t slot;           // adjoint: gradient slot of this gate, or -1
+    double u[8];            // 2x2 complex (re, im) row-major
+    double d[8];            // adjoint: derivative generator D (dU = D U)
+};
+
+// A diagonal term: amplitude x is multiplied by `val` (or negated for
+// RT_SIGNS) iff (x & qmask) == qmask.  The mask is split by where the bits
+// live in the tile: lane bits, register slots (expanded to the set of
+// register indices it selects) and bits outside the tile.
+struct DiagTerm {           // 48 bytes
+    uint64_t outside;       // global bits outside the tile
+    uint64_t regset;        // bit r set if register index r matches
+    uint32_t lanemask;      // lane bits (0..5)
+    uint32_t pad;
+    double val[2];          // phase (RT_PHASE)
+    uint64_t pad2;
+};
+
+struct RTHeader {           // 64 bytes
+    int32_t nops;
+    int32_t vbits;
+    int32_t rq[8];          // register qubits, ascending
+    int32_t nterms;
+    int32_t op_off;         // byte offset of the RTOp array from the header
+    int32_t term_off;       // byte offset of the DiagTerm array
+    int32_t pad[3];
+};
+
+// LDS-tile ops
+enum LTKind : int32_t {
+    LT_BLOCK = 1,           // dense 2^k block on local positions pos[0..k-1]
+    LT_SIGNS = 2,           // sign flips (terms use local masks)
+    LT_PHASE = 3,           // general diagonal phase term
+};
+
+struct LTOp {               // 64 bytes
+    int32_t kind;
+    int32_t k;
+    int32_t pos[5];         // ascending local bit positions
+    int32_t mat_off;        // byte offset of the matrix from the header
+    int32_t nterms;
+    int32_t term0;
+    int32_t pad[6];
+};
+
+struct LTTerm {             // 32 bytes
+    uint64_t outside;       // global bits outside the tile
+    uint32_t localmask;     // local bits of the tile index
+    uint32_t itset;         // per-thread element slots i (local index
+                            // t + 256 i) whose bits 8.. match localmask
+    double val[2];
+};
+
+struct LTHeader {           // 64 bytes
+    int32_t nops;
+    int32_t mbits;          // tile = 2^mbits amplitudes
+    int32_t hq[8];          // gathered (non-lane) qubits, ascending
+    int32_t op_off;
+    int32_t term_off;
+    int32_t pad[4];
+};
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+enum OpType : int32_t {
+    OP_INIT_UNIFORM = 1,    // psi_x = 2^{-n/2} (Hadamard layer on |0..0>)
+    OP_INIT_ZERO,           // psi = |0..0>
+    OP_PLAIN_1Q,            // dense 2x2 on q0, full sweep
+    OP_PLAIN_CZ,            // controlled-Z as a controlled dense gate
+    OP_SPEC_DENSE,          // dense 2x2, general complex
+    OP_SPEC_REAL,           // dense 2x2 with real entries (e.g. H, Y^1/2)
+    OP_SPEC_DIAG,           // multiply amplitudes with bit q0 set by m[3]
+    OP_SPEC_CZ,             // negate amplitudes with bits q0 and q1 set
+    OP_REGTILE,             // register-tile program
+    OP_LDSTILE,             // LDS-tile program
+    OP_ADJ_REGTILE,         // adjoint register-tile program (phi and mu)
+    OP_CKPT_STORE,          // copy the state to checkpoint q0 (complex64)
+    OP_CKPT_LOAD,           // overwrite the state with checkpoint q0
+};
+
+struct Op {
+    OpType type;
+    int32_t q0 = -1, q1 = -1;
+    M2 u{};
+    int32_t vbits = 0;      // REGTILE: register qubits; LDSTILE: tile bits
+    size_t prog_off = 0;    // byte offset in the plan's program buffer
+    double bytes = 0;       // algorithmic HBM bytes of this sweep
+    int32_t mfma = 0;       // LDSTILE program uses matrix-core blocks
+};
+
+struct Plan {
+    std::vector<Op> ops;
+    std::vector<Op> bops;        // adjoint: backward sweep sequence
+    std::vector<int> slot_param; // adjoint: parameter index of each slot
+    int ncheckpoints = 0;
+    std::vector<uint8_t> prog;   // host copy of all tile programs
+    void *dprog = nullptr;       // device copy
+    int64_t sweeps = 0;
+    double bytes = 0;
+    int n = 0;
+    int dtype = 0;
+    ~Plan();
+};
+
+// Gate after specialisation.
+enum SKind { SG_DENSE = 0, SG_DIAG1 = 1, SG_CZ = 2 };
+struct SGate {
+    int kind;
+    int q0, q1;
+    M2 u;            // dense: 2x2; diag1: diag(u.m[0], u.m[3])
+    int src;         // index of the source gate
+    int slot = -1;   // parametrised gate: its gradient slot (list order)
+    M2 d{};          // derivative generator of a parametrised gate
+};
+
+struct PlanRequest {
+    int n;
+    int dtype;           // sv_dtype
+    int mode;
+    int k_max;
+    int tile;            // tile qubits (TILED) / register qubits (REGTILE)
+    bool from_zero;      // state is |0..0>: a leading Hadamard layer may be
+                         // replaced by the uniform initialisation
+    bool force_zero;     // the plan must itself start from |0..0>
+};
+
+// Validate the circuit and produce the specialised gate list in order.
+sv_status specialise(const sv_circuit *c, int n, std::vector<SGate> *out);
+// Fold single-qubit diagonal gates into neighbouring dense gates on the
+// same qubit (exact algebra, FP64).  With param_safe, parametrised gates
+// are never folded and a diagonal is folded into a parametrised gate only
+// on the side that keeps dU = D U valid.
+void fold_diagonals(std::vector<SGate> *g, int n, bool param_safe = false);
+sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan);
+// Forward and backward sweep sequences of the adjoint gradient, with a
+// checkpoint after every checkpoint_c cycles (0 = none).
+sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int checkpoint_c,
+                             Plan *plan);
+double state_bytes(int n, int dtype);
+
+// ---------------------------------------------------------------------------
+// state handle
+// ---------------------------------------------------------------------------
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    sv_status reserve(size_t need);
+    ~Workspace();
+};
+
+}  // namespace svi
+
+struct sv_state {
+    int n = 0;
+    sv_dtype dt = SV_C64;
+    void *data = nullptr;
+    bool owned = false;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool known_zero = false;     // contents are |0..0>
+    svi::Workspace ws;           // reductions, sampler
+    svi::Workspace ws2;          // adjoint second state / checkpoints
+    std::map<std::string, std::shared_ptr<svi::Plan>> plans;
+};
+
+namespace svi {
+
+// ---------------------------------------------------------------------------
+// launchers (sweeps.hip)
+// ---------------------------------------------------------------------------
+sv_status launch_op(sv_state *st, const Plan &plan, const Op &op, void *psi);
+sv_status get_plan(sv_state *st, const sv_circuit *c, PlanRequest rq, std::shared_ptr<Plan> *out);
+sv_status run_plan(sv_state *st, const Plan &plan);
+sv_status launch_init_zero(sv_state *st, void *psi);
+sv_status upload_plan(sv_state *st, Plan *plan);
+
+// reductions (reduce.hip)
+sv_status run_probs(sv_state *st, uint64_t begin, uint64_t count, int f64, void *out);
+sv_status run_stats(sv_state *st, const void *psi, sv_stats *out);
+sv_status run_norm(sv_state *st, const void *psi, double *S);
+sv_status run_sample(sv_state *st, const void *psi, int64_t k, uint64_t seed,
+                     uint64_t *dev_out);
+sv_status run_sample_from(const double *probs, uint64_t N, const uint64_t *r64,
+                          int64_t k, uint64_t *out, hipStream_t s);
+sv_status run_cross_entropy(sv_state *st, const void *psi, const uint64_t *dev_samples,
+                            int64_t k, double S, double *sum_log, int64_t *zeros);
+
+std::string plan_key(const sv_circuit *c, const PlanRequest &rq);
+
+}  // namespace svi

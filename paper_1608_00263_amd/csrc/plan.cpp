@@ -1,0 +1,883 @@
+// Host planner: gate records -> sweeps over the state.
+//
+// Every sweep reads and writes the whole state once, so the planner's job
+// is to apply as many gates as possible per sweep (the role cache blocking
+// and gate specialisation play in App. B, "Implementation and
+// Optimization"):
+//  * specialisation: H and Y^1/2 are real, T/S/Z/P and CZ are diagonal;
+//  * diagonal folding: a single-qubit diagonal gate commutes with every
+//    other diagonal gate, so it is multiplied (in FP64) into the next dense
+//    gate on its qubit, or the previous one; CZ gates stay as sign flips
+//    that any sweep can apply, because every amplitude's full index is
+//    known inside a tile;
+//  * a leading Hadamard layer on |0..0> becomes the uniform state;
+//  * register tiles: gates on qubits 0..5 (the lanes of a wavefront) and on
+//    a few gathered qubits held in registers run without leaving the chip;
+//  * fused blocks: runs of gates on at most k_max qubits are multiplied into
+//    one dense 2^k x 2^k unitary (FP64, rounded once to the state precision);
+//  * LDS tiles: several fused blocks whose qubits fit one 2^m tile share a
+//    sweep.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <functional>
+#include <set>
+#include <sstream>
+
+#include "internal.h"
+
+namespace svi {
+
+M2 m2_mul(const M2 &a, const M2 &b) {
+    M2 r;
+    r.m[0] = cadd(cmul(a.m[0], b.m[0]), cmul(a.m[1], b.m[2]));
+    r.m[1] = cadd(cmul(a.m[0], b.m[1]), cmul(a.m[1], b.m[3]));
+    r.m[2] = cadd(cmul(a.m[2], b.m[0]), cmul(a.m[3], b.m[2]));
+    r.m[3] = cadd(cmul(a.m[2], b.m[1]), cmul(a.m[3], b.m[3]));
+    return r;
+}
+
+M2 m2_dag(const M2 &a) {
+    M2 r;
+    r.m[0] = cconj(a.m[0]);
+    r.m[1] = cconj(a.m[2]);
+    r.m[2] = cconj(a.m[1]);
+    r.m[3] = cconj(a.m[3]);
+    return r;
+}
+
+static M2 mk(cd a, cd b, cd c, cd d) {
+    M2 r;
+    r.m[0] = a; r.m[1] = b; r.m[2] = c; r.m[3] = d;
+    return r;
+}
+
+// RX(a) = exp(-i a X / 2), RY(a) = exp(-i a Y / 2), P(a) = diag(1, e^{ia})
+static M2 rot_x(double a) {
+    double c = std::cos(0.5 * a), s = std::sin(0.5 * a);
+    return mk({c, 0}, {0, -s}, {0, -s}, {c, 0});
+}
+static M2 rot_y(double a) {
+    double c = std::cos(0.5 * a), s = std::sin(0.5 * a);
+    return mk({c, 0}, {-s, 0}, {s, 0}, {c, 0});
+}
+static M2 phase_gate(double a) { return mk({1, 0}, {0, 0}, {0, 0}, {std::cos(a), std::sin(a)}); }
+
+bool gate_matrix(int kind, double th, const double *mat8, M2 *out) {
+    const double pi = M_PI;
+    const double r = 1.0 / std::sqrt(2.0);
+    switch (kind) {
+    case SV_H: *out = mk({r, 0}, {r, 0}, {r, 0}, {-r, 0}); return true;
+    case SV_T: *out = phase_gate(pi / 4 + th); return true;
+    case SV_TDG: *out = phase_gate(-pi / 4 + th); return true;
+    case SV_S: *out = mk({1, 0}, {0, 0}, {0, 0}, {0, 1}); return true;
+    case SV_SDG: *out = mk({1, 0}, {0, 0}, {0, 0}, {0, -1}); return true;
+    case SV_Z: *out = mk({1, 0}, {0, 0}, {0, 0}, {-1, 0}); return true;
+    case SV_X: *out = mk({0, 0}, {1, 0}, {1, 0}, {0, 0}); return true;
+    case SV_Y: *out = mk({0, 0}, {0, -1}, {0, 1}, {0, 0}); return true;
+    case SV_SX: *out = rot_x(pi / 2 + th); return true;
+    case SV_SXDG: *out = rot_x(-pi / 2 + th); return true;
+    case SV_SY: *out = rot_y(pi / 2 + th); return true;
+    case SV_SYDG: *out = rot_y(-pi / 2 + th); return true;
+    case SV_U1:
+        if (!mat8) return false;
+        for (int i = 0; i < 4; i++) out->m[i] = {mat8[2 * i], mat8[2 * i + 1]};
+        return true;
+    default: return false;
+    }
+}
+
+bool derivative_generator(int kind, M2 *out) {
+    switch (kind) {
+    case SV_SX: case SV_SXDG: *out = mk({0, 0}, {0, -0.5}, {0, -0.5}, {0, 0}); return true;
+    case SV_SY: case SV_SYDG: *out = mk({0, 0}, {-0.5, 0}, {0.5, 0}, {0, 0}); return true;
+    case SV_T: case SV_TDG: *out = mk({0, 0}, {0, 0}, {0, 0}, {0, 1}); return true;
+    default: return false;
+    }
+}
+
+static bool is_diag(const M2 &u) {
+    return u.m[1].re == 0 && u.m[1].im == 0 && u.m[2].re == 0 && u.m[2].im == 0;
+}
+static bool is_real(const M2 &u) {
+    return u.m[0].im == 0 && u.m[1].im == 0 && u.m[2].im == 0 && u.m[3].im == 0;
+}
+
+double state_bytes(int n, int dtype) { return std::ldexp(dtype == SV_C64 ? 8.0 : 16.0, n); }
+
+sv_status specialise(const sv_circuit *c, int n, std::vector<SGate> *out) {
+    out->clear();
+    out->reserve((size_t)c->ngates);
+    int nslot = 0;
+    for (int64_t i = 0; i < c->ngates; i++) {
+        const sv_gate &g = c->gates[i];
+        char buf[160];
+        if (g.q0 < 0 || g.q0 >= n) {
+            snprintf(buf, sizeof buf, "gate %lld: qubit %d out of range", (long long)i, g.q0);
+            return fail(SV_EINVAL, buf);
+        }
+        if (g.kind == SV_CZ) {
+            if (g.q1 < 0 || g.q1 >= n || g.q1 == g.q0 || g.param >= 0) {
+                snprintf(buf, sizeof buf, "gate %lld: bad CZ qubits (%d, %d)", (long long)i, g.q0, g.q1);
+                return fail(SV_EINVAL, buf);
+            }
+            SGate s{};
+            s.kind = SG_CZ;
+            s.q0 = std::min(g.q0, g.q1);
+            s.q1 = std::max(g.q0, g.q1);
+            s.src = (int)i;
+            out->push_back(s);
+            continue;
+        }
+        double th = 0;
+        if (g.param >= 0) {
+            bool rot = g.kind == SV_T || g.kind == SV_SX || g.kind == SV_SY || g.kind == SV_TDG ||
+                       g.kind == SV_SXDG || g.kind == SV_SYDG;
+            if (!rot || g.param >= c->nparams || !c->theta) {
+                snprintf(buf, sizeof buf, "gate %lld: bad parameter %d for kind %d", (long long)i,
+                         g.param, g.kind);
+                return fail(SV_EINVAL, buf);
+            }
+            th = c->theta[g.param];
+        }
+        const double *mat = nullptr;
+        if (g.kind == SV_U1) {
+            if (g.mat < 0 || g.mat >= c->nmats || !c->mats) {
+                snprintf(buf, sizeof buf, "gate %lld: bad matrix index %d", (long long)i, g.mat);
+                return fail(SV_EINVAL, buf);
+            }
+            mat = c->mats + 8 * g.mat;
+        }
+        SGate s{};
+        if (!gate_matrix(g.kind, th, mat, &s.u)) {
+            snprintf(buf, sizeof buf, "gate %lld: unknown kind %d", (long long)i, g.kind);
+            return fail(SV_EINVAL, buf);
+        }
+        s.kind = is_diag(s.u) ? SG_DIAG1 : SG_DENSE;
+        s.q0 = g.q0;
+        s.q1 = -1;
+        s.src = (int)i;
+        if (g.param >= 0) {
+            s.slot = nslot++;
+            derivative_generator(g.kind, &s.d);
+        }
+        out->push_back(s);
+    }
+    return SV_OK;
+}
+
+void fold_diagonals(std::vector<SGate> *gl, int n, bool param_safe) {
+    std::vector<SGate> &g = *gl;
+    std::vector<char> dead(g.size(), 0);
+    // per qubit: indices of gates touching it, in order
+    std::vector<std::vector<int>> on(n);
+    for (int i = 0; i < (int)g.size(); i++) {
+        on[g[i].q0].push_back(i);
+        if (g[i].kind == SG_CZ) on[g[i].q1].push_back(i);
+    }
+    for (int q = 0; q < n; q++) {
+        const std::vector<int> &v = on[q];
+        for (size_t a = 0; a < v.size(); a++) {
+            int i = v[a];
+            if (g[i].kind != SG_DIAG1 || dead[i]) continue;
+            if (param_safe && g[i].slot >= 0) continue;
+            // next dense gate on q (diagonal gates in between commute); with
+            // dU = D U a diagonal may be folded into a parametrised gate only
+            // when it acts first
+            int target = -1;
+            bool before = true;
+            for (size_t b = a + 1; b < v.size(); b++)
+                if (g[v[b]].kind == SG_DENSE) { target = v[b]; break; }
+            if (target < 0) {
+                before = false;
+                for (size_t b = a; b-- > 0;)
+                    if (g[v[b]].kind == SG_DENSE) { target = v[b]; break; }
+                if (target >= 0 && param_safe && g[target].slot >= 0) target = -1;
+            }
+            if (target < 0) continue;   // no dense gate on q: stays a phase
+            M2 d = g[i].u;
+            g[target].u = before ? m2_mul(g[target].u, d) : m2_mul(d, g[target].u);
+            dead[i] = 1;
+        }
+    }
+    std::vector<SGate> out;
+    out.reserve(g.size());
+    for (size_t i = 0; i < g.size(); i++)
+        if (!dead[i]) out.push_back(g[i]);
+    g.swap(out);
+}
+
+// Leading Hadamard layer on |0..0>: the first gate on every qubit is H.
+static bool strip_hadamard_layer(std::vector<SGate> *gl, int n, const sv_circuit *c) {
+    std::vector<int> first(n, -1);
+    for (int i = 0; i < (int)gl->size(); i++) {
+        const SGate &s = (*gl)[i];
+        if (first[s.q0] < 0) first[s.q0] = i;
+        if (s.kind == SG_CZ && first[s.q1] < 0) first[s.q1] = i;
+    }
+    for (int q = 0; q < n; q++) {
+        int i = first[q];
+        if (i < 0) return false;
+        const SGate &s = (*gl)[i];
+        if (s.kind != SG_DENSE || s.q0 != q) return false;
+        const sv_gate &src = c->gates[s.src];
+        if (src.kind != SV_H) return false;
+    }
+    std::vector<char> drop(gl->size(), 0);
+    for (int q = 0; q < n; q++) drop[first[q]] = 1;
+    std::vector<SGate> out;
+    for (size_t i = 0; i < gl->size(); i++)
+        if (!drop[i]) out.push_back((*gl)[i]);
+    gl->swap(out);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// program buffer helpers
+// ---------------------------------------------------------------------------
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+template <typename S>
+static size_t push_struct(std::vector<uint8_t> *buf, const S &s) {
+    size_t off = align_up(buf->size(), 16);
+    buf->resize(off + sizeof(S));
+    std::memcpy(buf->data() + off, &s, sizeof(S));
+    return off;
+}
+
+static size_t push_bytes(std::vector<uint8_t> *buf, const void *p, size_t bytes) {
+    size_t off = align_up(buf->size(), 16);
+    buf->resize(off + bytes);
+    if (bytes) std::memcpy(buf->data() + off, p, bytes);
+    return off;
+}
+
+// ---------------------------------------------------------------------------
+// register tiles
+// ---------------------------------------------------------------------------
+struct Sweep {
+    std::vector<int> tile;     // gathered qubits (>= LANE_BITS), ascending
+    std::vector<int> items;    // indices into the gate / block list, in order
+};
+
+// Greedy grouping of an ordered list of items into sweeps.  An item is
+// either "diagonal" (applicable in any sweep) or needs all of `need(i)` in
+// the sweep's qubit set, which holds qubits 0..5 plus at most `cap`
+// gathered ones.  Items are taken in list order; an item that cannot be
+// taken blocks its qubits for the rest of the sweep (a skipped diagonal
+// item blocks only non-diagonal items on its qubits, since diagonal items
+// commute).
+static std::vector<Sweep> group_sweeps(int nitems, int n, int cap,
+                                       const std::function<bool(int)> &diag,
+                                       const std::function<std::vector<int>(int)> &qubits) {
+    std::vector<Sweep> out;
+    std::vector<char> done(nitems, 0);
+    int left = nitems;
+    std::vector<char> block_all(n), block_dense(n), in_tile(n);
+    while (left > 0) {
+        Sweep sw;
+        std::fill(block_all.begin(), block_all.end(), 0);
+        std::fill(block_dense.begin(), block_dense.end(), 0);
+        std::fill(in_tile.begin(), in_tile.end(), 0);
+        for (int q = 0; q < std::min(n, LANE_BITS); q++) in_tile[q] = 1;
+        int ngather = 0;
+        for (int i = 0; i < nitems; i++) {
+            if (done[i]) continue;
+            std::vector<int> qs = qubits(i);
+            bool d = diag(i);
+            bool ok = true;
+            for (int q : qs)
+                if (block_all[q] || (!d && block_dense[q])) ok = false;
+            if (ok && !d) {
+                int need = 0;
+                for (int q : qs)
+                    if (!in_tile[q]) need++;
+                if (ngather + need > cap) ok = false;
+                else
+                    for (int q : qs)
+                        if (!in_tile[q]) { in_tile[q] = 1; sw.tile.push_back(q); ngather++; }
+            }
+            if (ok) {
+                sw.items.push_back(i);
+                done[i] = 1;
+                left--;
+            } else if (d) {
+                for (int q : qs) block_dense[q] = 1;
+            } else {
+                for (int q : qs) block_all[q] = 1;
+            }
+        }
+        std::sort(sw.tile.begin(), sw.tile.end());
+        out.push_back(sw);
+    }
+    return out;
+}
+
+static uint64_t bit64(int q) { return (uint64_t)1 << q; }
+
+struct RTProgram {
+    RTHeader h{};
+    std::vector<RTOp> ops;
+    std::vector<DiagTerm> terms;
+};
+
+static void put_mat(double *dst, const M2 &m) {
+    for (int i = 0; i < 4; i++) { dst[2 * i] = m.m[i].re; dst[2 * i + 1] = m.m[i].im; }
+}
+
+static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int vbits, int n) {
+    RTProgram P;
+    RTHeader &h = P.h;
+    h.vbits = vbits;
+    // unused register slots are filled with further qubits so that every
+    // tile covers 2^(6+vbits) distinct amplitudes
+    std::vector<int> rq(sw.tile.begin(), sw.tile.end());
+    for (int q = LANE_BITS; (int)rq.size() < vbits && q < n; q++)
+        if (std::find(rq.begin(), rq.end(), q) == rq.end()) rq.push_back(q);
+    std::sort(rq.begin(), rq.end());
+    std::vector<int> slot(64, -1);
+    for (int i = 0; i < 8; i++) h.rq[i] = i < (int)rq.size() ? rq[i] : -1;
+    for (size_t i = 0; i < rq.size(); i++) slot[rq[i]] = (int)i;
+    std::vector<RTOp> &ops = P.ops;
+    std::vector<DiagTerm> &terms = P.terms;
+    auto term_for = [&](uint64_t mask) {
+        DiagTerm t{};
+        uint32_t rbits = 0;
+        for (int q = 0; q < 64; q++) {
+            if (!(mask & bit64(q))) continue;
+            if (q < LANE_BITS) t.lanemask |= 1u << q;
+            else if (slot[q] >= 0) rbits |= 1u << slot[q];
+            else t.outside |= bit64(q);
+        }
+        for (int r = 0; r < (1 << vbits); r++)
+            if ((r & rbits) == rbits) t.regset |= (uint64_t)1 << r;
+        return t;
+    };
+    for (int idx : sw.items) {
+        const SGate &s = g[idx];
+        if (s.kind == SG_DENSE) {
+            RTOp o{};
+            if (s.q0 < LANE_BITS) { o.kind = RT_LANE; o.a = s.q0; }
+            else { o.kind = RT_REG; o.a = slot[s.q0]; }
+            put_mat(o.u, s.u);
+            o.slot = s.slot;
+            put_mat(o.d, s.d);
+            ops.push_back(o);
+        } else if (s.kind == SG_CZ) {
+            DiagTerm t = term_for(bit64(s.q0) | bit64(s.q1));
+            if (!ops.empty() && ops.back().kind == RT_SIGNS &&
+                ops.back().a + ops.back().nterms == (int)terms.size()) {
+                ops.back().nterms++;
+            } else {
+                RTOp o{};
+                o.kind = RT_SIGNS;
+                o.a = (int)terms.size();
+                o.nterms = 1;
+                o.slot = -1;
+                ops.push_back(o);
+            }
+            terms.push_back(t);
+        } else {
+            // single-qubit diagonal diag(d0, d1) left unfolded: the ratio
+            // d1 / d0 on amplitudes with the bit set, then d0 on all of them
+            DiagTerm t = term_for(bit64(s.q0));
+            cd d0 = s.u.m[0], d1 = s.u.m[3];
+            double den = d0.re * d0.re + d0.im * d0.im;
+            cd ratio = {(d1.re * d0.re + d1.im * d0.im) / den, (d1.im * d0.re - d1.re * d0.im) / den};
+            t.val[0] = ratio.re;
+            t.val[1] = ratio.im;
+            RTOp o{};
+            o.kind = RT_PHASE;
+            o.a = (int)terms.size();
+            o.nterms = 1;
+            o.slot = s.slot;
+            put_mat(o.d, s.d);
+            terms.push_back(t);
+            ops.push_back(o);
+            if (d0.re != 1.0 || d0.im != 0.0) {
+                DiagTerm all = term_for(0);
+                all.val[0] = d0.re;
+                all.val[1] = d0.im;
+                RTOp o2{};
+                o2.kind = RT_PHASE;
+                o2.a = (int)terms.size();
+                o2.nterms = 1;
+                o2.slot = -1;
+                terms.push_back(all);
+                ops.push_back(o2);
+            }
+        }
+    }
+    return P;
+}
+
+// The adjoint of a register-tile program: ops reversed, matrices and phases
+// conjugate-transposed; gradient slots and generators stay with their ops.
+static RTProgram reverse_regtile(const RTProgram &F) {
+    RTProgram B = F;
+    std::reverse(B.ops.begin(), B.ops.end());
+    for (RTOp &o : B.ops) {
+        if (o.kind == RT_REG || o.kind == RT_LANE) {
+            M2 u;
+            for (int i = 0; i < 4; i++) u.m[i] = {o.u[2 * i], o.u[2 * i + 1]};
+            put_mat(o.u, m2_dag(u));
+        }
+    }
+    for (DiagTerm &t : B.terms) t.val[1] = -t.val[1];
+    return B;
+}
+
+static void push_regtile(const RTProgram &P, int n, int dtype, OpType type, std::vector<Op> *seq,
+                         Plan *plan) {
+    RTHeader h = P.h;
+    h.nops = (int)P.ops.size();
+    h.nterms = (int)P.terms.size();
+    size_t hoff = push_struct(&plan->prog, h);
+    size_t ooff = push_bytes(&plan->prog, P.ops.data(), P.ops.size() * sizeof(RTOp));
+    size_t toff = push_bytes(&plan->prog, P.terms.data(), P.terms.size() * sizeof(DiagTerm));
+    RTHeader *hp = reinterpret_cast<RTHeader *>(plan->prog.data() + hoff);
+    hp->op_off = (int32_t)(ooff - hoff);
+    hp->term_off = (int32_t)(toff - hoff);
+    Op op;
+    op.type = type;
+    op.vbits = P.h.vbits;
+    op.prog_off = hoff;
+    op.bytes = (type == OP_ADJ_REGTILE ? 4 : 2) * state_bytes(n, dtype);
+    seq->push_back(op);
+}
+
+static void emit_regtile(const std::vector<SGate> &g, const Sweep &sw, int vbits, int n, int dtype,
+                         Plan *plan) {
+    push_regtile(build_regtile(g, sw, vbits, n), n, dtype, OP_REGTILE, &plan->ops, plan);
+}
+
+// ---------------------------------------------------------------------------
+// fused blocks
+// ---------------------------------------------------------------------------
+struct Block {
+    std::vector<int> qubits;   // ascending
+    std::vector<int> gates;    // indices into the specialised list, in order
+    bool diag = true;
+};
+
+static std::vector<Block> fuse_blocks(const std::vector<SGate> &g, int n, int kmax) {
+    std::vector<Block> blocks;
+    std::vector<int> last(n, -1);
+    for (int i = 0; i < (int)g.size(); i++) {
+        const SGate &s = g[i];
+        std::vector<int> qs = {s.q0};
+        if (s.kind == SG_CZ) qs.push_back(s.q1);
+        int lmin = -1;
+        for (int q : qs) lmin = std::max(lmin, last[q]);
+        int best = -1, best_overlap = -1;
+        int lo = std::max(lmin, (int)blocks.size() - 64);
+        for (int b = (int)blocks.size() - 1; b >= std::max(lo, 0); b--) {
+            const Block &B = blocks[b];
+            int overlap = 0, uni = (int)B.qubits.size();
+            for (int q : qs) {
+                if (std::find(B.qubits.begin(), B.qubits.end(), q) != B.qubits.end()) overlap++;
+                else uni++;
+            }
+            if (uni > kmax) continue;
+            if (overlap > best_overlap) { best = b; best_overlap = overlap; }
+        }
+        if (best < 0) {
+            blocks.push_back(Block());
+            best = (int)blocks.size() - 1;
+        }
+        Block &B = blocks[best];
+        for (int q : qs)
+            if (std::find(B.qubits.begin(), B.qubits.end(), q) == B.qubits.end()) B.qubits.push_back(q);
+        std::sort(B.qubits.begin(), B.qubits.end());
+        B.gates.push_back(i);
+        if (s.kind == SG_DENSE) B.diag = false;
+        for (int q : qs) last[q] = best;
+    }
+    return blocks;
+}
+
+// Dense 2^k x 2^k matrix of a block (row-major, complex FP64); matrix bit j
+// is block qubit j.
+static std::vector<cd> block_matrix(const std::vector<SGate> &g, const Block &B) {
+    int k = (int)B.qubits.size();
+    int d = 1 << k;
+    std::vector<cd> M(d * d, cd{0, 0});
+    for (int i = 0; i < d; i++) M[i * d + i] = {1, 0};
+    auto pos = [&](int q) {
+        return (int)(std::find(B.qubits.begin(), B.qubits.end(), q) - B.qubits.begin());
+    };
+    for (int gi : B.gates) {
+        const SGate &s = g[gi];
+        if (s.kind == SG_CZ) {
+            int m = (1 << pos(s.q0)) | (1 << pos(s.q1));
+            for (int r = 0; r < d; r++)
+                if ((r & m) == m)
+                    for (int c = 0; c < d; c++) M[r * d + c] = {-M[r * d + c].re, -M[r * d + c].im};
+            continue;
+        }
+        int b = 1 << pos(s.q0);
+        for (int c = 0; c < d; c++)
+            for (int r0 = 0; r0 < d; r0++) {
+                if (r0 & b) continue;
+                int r1 = r0 | b;
+                cd a0 = M[r0 * d + c], a1 = M[r1 * d + c];
+                M[r0 * d + c] = cadd(cmul(s.u.m[0], a0), cmul(s.u.m[1], a1));
+                M[r1 * d + c] = cadd(cmul(s.u.m[2], a0), cmul(s.u.m[3], a1));
+            }
+    }
+    return M;
+}
+
+// Diagonal of an all-diagonal block as (mask, factor) terms: sign flips for
+// CZ, phases for the rest.
+static void diag_terms(const std::vector<SGate> &g, const Block &B,
+                       std::vector<std::pair<uint64_t, cd>> *out) {
+    for (int gi : B.gates) {
+        const SGate &s = g[gi];
+        if (s.kind == SG_CZ) {
+            out->push_back({bit64(s.q0) | bit64(s.q1), cd{-1, 0}});
+        } else {
+            cd d0 = s.u.m[0], d1 = s.u.m[3];
+            double den = d0.re * d0.re + d0.im * d0.im;
+            cd ratio = {(d1.re * d0.re + d1.im * d0.im) / den, (d1.im * d0.re - d1.re * d0.im) / den};
+            out->push_back({bit64(s.q0), ratio});
+            if (d0.re != 1.0 || d0.im != 0.0) out->push_back({0, d0});
+        }
+    }
+}
+
+struct LTItem {          // an op of an LDS tile program before encoding
+    int kind;            // 0 block, 1 diag
+    const Block *blk;
+};
+
+static void emit_ldstile(const std::vector<SGate> &g, const std::vector<const Block *> &items,
+                         const std::vector<int> &tile, int mbits, int n, int dtype, Plan *plan) {
+    LTHeader h{};
+    h.mbits = mbits;
+    std::vector<int> hq(tile.begin(), tile.end());
+    for (int q = LANE_BITS; (int)hq.size() < mbits - LANE_BITS && q < n; q++)
+        if (std::find(hq.begin(), hq.end(), q) == hq.end()) hq.push_back(q);
+    std::sort(hq.begin(), hq.end());
+    std::vector<int> local(64, -1);
+    for (int q = 0; q < LANE_BITS; q++) local[q] = q;
+    for (size_t i = 0; i < hq.size(); i++) {
+        h.hq[i] = hq[i];
+        local[hq[i]] = LANE_BITS + (int)i;
+    }
+    for (size_t i = hq.size(); i < 8; i++) h.hq[i] = -1;
+    std::vector<LTOp> ops;
+    std::vector<LTTerm> terms;
+    std::vector<std::pair<size_t, std::vector<cd>>> mats;   // (op index, matrix)
+    bool mfma = false;
+    for (const Block *B : items) {
+        if (B->diag) {
+            std::vector<std::pair<uint64_t, cd>> dt;
+            diag_terms(g, *B, &dt);
+            for (auto &mt : dt) {
+                LTTerm t{};
+                for (int q = 0; q < 64; q++) {
+                    if (!(mt.first & bit64(q))) continue;
+                    if (local[q] >= 0) t.localmask |= 1u << local[q];
+                    else t.outside |= bit64(q);
+                }
+                t.val[0] = mt.second.re;
+                t.val[1] = mt.second.im;
+                {
+                    int per = 1 << (mbits - 8);
+                    uint32_t hi = t.localmask & ~0xFFu;
+                    for (int i = 0; i < per; i++)
+                        if ((((uint32_t)i << 8) & hi) == hi) t.itset |= 1u << i;
+                }
+                bool sign = mt.second.re == -1.0 && mt.second.im == 0.0;
+                int kind = sign ? LT_SIGNS : LT_PHASE;
+                if (!ops.empty() && ops.back().kind == kind &&
+                    ops.back().term0 + ops.back().nterms == (int)terms.size()) {
+                    ops.back().nterms++;
+                } else {
+                    LTOp o{};
+                    o.kind = kind;
+                    o.term0 = (int)terms.size();
+                    o.nterms = 1;
+                    ops.push_back(o);
+                }
+                terms.push_back(t);
+            }
+            continue;
+        }
+        LTOp o{};
+        o.kind = LT_BLOCK;
+        o.k = (int)B->qubits.size();
+        for (int j = 0; j < o.k; j++) o.pos[j] = local[B->qubits[j]];
+        if (o.k >= 4 && dtype == SV_C64) mfma = true;
+        mats.push_back({ops.size(), block_matrix(g, *B)});
+        ops.push_back(o);
+    }
+    h.nops = (int)ops.size();
+    size_t hoff = push_struct(&plan->prog, h);
+    // matrices in the state precision
+    for (auto &pm : mats) {
+        size_t off;
+        if (dtype == SV_C64) {
+            std::vector<float> f(pm.second.size() * 2);
+            for (size_t i = 0; i < pm.second.size(); i++) {
+                f[2 * i] = (float)pm.second[i].re;
+                f[2 * i + 1] = (float)pm.second[i].im;
+            }
+            off = push_bytes(&plan->prog, f.data(), f.size() * sizeof(float));
+        } else {
+            off = push_bytes(&plan->prog, pm.second.data(), pm.second.size() * sizeof(cd));
+        }
+        ops[pm.first].mat_off = (int32_t)(off - hoff);
+    }
+    size_t ooff = push_bytes(&plan->prog, ops.data(), ops.size() * sizeof(LTOp));
+    size_t toff = push_bytes(&plan->prog, terms.data(), terms.size() * sizeof(LTTerm));
+    LTHeader *hp = reinterpret_cast<LTHeader *>(plan->prog.data() + hoff);
+    hp->op_off = (int32_t)(ooff - hoff);
+    hp->term_off = (int32_t)(toff - hoff);
+    Op op;
+    op.type = OP_LDSTILE;
+    op.vbits = mbits;
+    op.prog_off = hoff;
+    op.mfma = mfma;
+    op.bytes = 2 * state_bytes(n, dtype);
+    plan->ops.push_back(op);
+}
+
+// ---------------------------------------------------------------------------
+// per-gate plans
+// ---------------------------------------------------------------------------
+static double diag_bytes(int n, int dtype, int q) {
+    int line_bits = dtype == SV_C64 ? 4 : 3;   // 128-byte lines
+    double S = state_bytes(n, dtype);
+    return q >= line_bits ? S : 2 * S;
+}
+
+static double cz_bytes(int n, int dtype, int a, int b) {
+    int line_bits = dtype == SV_C64 ? 4 : 3;
+    double S = state_bytes(n, dtype);
+    int hi = (a >= line_bits) + (b >= line_bits);
+    return hi == 2 ? S / 2 : hi == 1 ? S : 2 * S;
+}
+
+static void plan_per_gate(const sv_circuit *c, const std::vector<SGate> &g, const PlanRequest &rq,
+                          Plan *plan) {
+    double S = state_bytes(rq.n, rq.dtype);
+    for (const SGate &s : g) {
+        Op op;
+        op.q0 = s.q0;
+        op.q1 = s.q1;
+        op.u = s.u;
+        if (rq.mode == SV_MODE_PLAIN) {
+            if (s.kind == SG_CZ) { op.type = OP_PLAIN_CZ; op.bytes = S; }
+            else { op.type = OP_PLAIN_1Q; op.bytes = 2 * S; }
+        } else if (s.kind == SG_CZ) {
+            op.type = OP_SPEC_CZ;
+            op.bytes = cz_bytes(rq.n, rq.dtype, s.q0, s.q1);
+        } else if (s.kind == SG_DIAG1) {
+            op.type = OP_SPEC_DIAG;
+            if (s.u.m[0].re != 1.0 || s.u.m[0].im != 0.0) {
+                // general diagonal: handled by the dense kernel
+                op.type = OP_SPEC_DENSE;
+                op.bytes = 2 * S;
+            } else {
+                op.bytes = diag_bytes(rq.n, rq.dtype, s.q0);
+            }
+        } else {
+            op.type = is_real(s.u) ? OP_SPEC_REAL : OP_SPEC_DENSE;
+            op.bytes = 2 * S;
+        }
+        plan->ops.push_back(op);
+    }
+    (void)c;
+}
+
+std::string plan_key(const sv_circuit *c, const PlanRequest &rq) {
+    // FNV-1a over the request, gate records, parameters and matrices
+    uint64_t h = 1469598103934665603ULL;
+    auto mix = [&](const void *p, size_t bytes) {
+        const uint8_t *b = (const uint8_t *)p;
+        for (size_t i = 0; i < bytes; i++) { h ^= b[i]; h *= 1099511628211ULL; }
+    };
+    mix(&rq, sizeof rq);
+    mix(&c->ngates, sizeof c->ngates);
+    mix(c->gates, sizeof(sv_gate) * (size_t)c->ngates);
+    if (c->nparams && c->theta) mix(c->theta, sizeof(double) * c->nparams);
+    if (c->nmats && c->mats) mix(c->mats, sizeof(double) * 8 * c->nmats);
+    std::ostringstream os;
+    os << std::hex << h << ":" << c->ngates;
+    return os.str();
+}
+
+Plan::~Plan() {
+    if (dprog) (void)hipFree(dprog);
+}
+
+sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
+    std::vector<SGate> g;
+    SV_TRY(specialise(c, rq.n, &g));
+    plan->n = rq.n;
+    plan->dtype = rq.dtype;
+    int mode = rq.mode;
+    // tile kernels need the 64 lanes of a wavefront plus gathered qubits
+    if ((mode == SV_MODE_REGTILE || mode == SV_MODE_FUSED || mode == SV_MODE_TILED) && rq.n < 10)
+        mode = SV_MODE_SPEC;
+    if (mode != SV_MODE_PLAIN && (rq.from_zero || rq.force_zero) &&
+        strip_hadamard_layer(&g, rq.n, c)) {
+        Op op;
+        op.type = OP_INIT_UNIFORM;
+        op.bytes = state_bytes(rq.n, rq.dtype);
+        plan->ops.push_back(op);
+    } else if (rq.force_zero) {
+        Op op;
+        op.type = OP_INIT_ZERO;
+        op.bytes = state_bytes(rq.n, rq.dtype);
+        plan->ops.push_back(op);
+    }
+    if (mode == SV_MODE_PLAIN || mode == SV_MODE_SPEC) {
+        PlanRequest r2 = rq;
+        r2.mode = mode;
+        plan_per_gate(c, g, r2, plan);
+    } else if (mode == SV_MODE_REGTILE) {
+        fold_diagonals(&g, rq.n);
+        int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 5 : 4);
+        vb = std::max(1, std::min(vb, rq.dtype == SV_C64 ? 6 : 5));
+        vb = std::min(vb, rq.n - LANE_BITS);
+        auto sweeps = group_sweeps(
+            (int)g.size(), rq.n, vb, [&](int i) { return g[i].kind != SG_DENSE; },
+            [&](int i) {
+                std::vector<int> q = {g[i].q0};
+                if (g[i].kind == SG_CZ) q.push_back(g[i].q1);
+                return q;
+            });
+        for (const Sweep &sw : sweeps) emit_regtile(g, sw, vb, rq.n, rq.dtype, plan);
+    } else {
+        fold_diagonals(&g, rq.n);
+        int kmax = rq.k_max > 0 ? std::min(rq.k_max, 5) : 4;
+        std::vector<Block> blocks = fuse_blocks(g, rq.n, kmax);
+        int mmax = rq.dtype == SV_C64 ? 13 : 12;
+        if (mode == SV_MODE_FUSED) {
+            // one sweep per dense block; diagonal blocks ride along with the
+            // next dense block (or the previous one at the end)
+            std::vector<const Block *> pending;
+            std::vector<std::vector<const Block *>> groups;
+            for (const Block &B : blocks) {
+                pending.push_back(&B);
+                if (!B.diag) { groups.push_back(pending); pending.clear(); }
+            }
+            if (!pending.empty()) {
+                if (groups.empty()) groups.push_back(pending);
+                else groups.back().insert(groups.back().end(), pending.begin(), pending.end());
+            }
+            for (auto &grp : groups) {
+                std::vector<int> tile;
+                for (const Block *B : grp)
+                    if (!B->diag)
+                        for (int q : B->qubits)
+                            if (q >= LANE_BITS) tile.push_back(q);
+                int m = std::max(LANE_BITS + (int)tile.size(), std::min(10, rq.n));
+                m = std::min(m, rq.n);
+                emit_ldstile(g, grp, tile, m, rq.n, rq.dtype, plan);
+            }
+        } else {
+            int m = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 12 : 11);
+            m = std::max(8, std::min(m, mmax));
+            m = std::min(m, rq.n);
+            int cap = m - LANE_BITS;
+            auto sweeps = group_sweeps(
+                (int)blocks.size(), rq.n, cap, [&](int i) { return blocks[i].diag; },
+                [&](int i) { return blocks[i].qubits; });
+            for (const Sweep &sw : sweeps) {
+                std::vector<const Block *> items;
+                for (int i : sw.items) items.push_back(&blocks[i]);
+                emit_ldstile(g, items, sw.tile, m, rq.n, rq.dtype, plan);
+            }
+        }
+    }
+    plan->sweeps = 0;
+    plan->bytes = 0;
+    for (const Op &op : plan->ops) {
+        plan->sweeps++;
+        plan->bytes += op.bytes;
+    }
+    return SV_OK;
+}
+
+static std::vector<Sweep> regtile_sweeps(const std::vector<SGate> &g, int n, int vb) {
+    return group_sweeps(
+        (int)g.size(), n, vb, [&](int i) { return g[i].kind != SG_DENSE; },
+        [&](int i) {
+            std::vector<int> q = {g[i].q0};
+            if (g[i].kind == SG_CZ) q.push_back(g[i].q1);
+            return q;
+        });
+}
+
+sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int checkpoint_c, Plan *plan) {
+    std::vector<SGate> g;
+    SV_TRY(specialise(c, rq.n, &g));
+    if (rq.n < 8) return fail(SV_ERANGE, "sv_backward needs n >= 8");
+    plan->n = rq.n;
+    plan->dtype = rq.dtype;
+    for (const SGate &s : g)
+        if (s.slot >= 0) plan->slot_param.push_back(c->gates[s.src].param);
+    for (int64_t i = 1; i < c->ngates; i++)
+        if (c->gates[i].cycle < c->gates[i - 1].cycle)
+            return fail(SV_EINVAL, "sv_backward: gate cycles must be nondecreasing");
+    if (strip_hadamard_layer(&g, rq.n, c)) {
+        Op op;
+        op.type = OP_INIT_UNIFORM;
+        op.bytes = state_bytes(rq.n, rq.dtype);
+        plan->ops.push_back(op);
+    } else {
+        return fail(SV_EINVAL, "sv_backward: the circuit must open with a Hadamard on every qubit");
+    }
+    fold_diagonals(&g, rq.n, true);
+    int vb = rq.tile > 0 ? rq.tile : 4;
+    vb = std::max(1, std::min(vb, rq.dtype == SV_C64 ? 5 : 4));
+    vb = std::min(vb, rq.n - LANE_BITS - 2);
+    // segments of consecutive gates between checkpoints
+    std::vector<std::vector<SGate>> segs(1);
+    int cur = 0;
+    for (const SGate &s : g) {
+        int cyc = c->gates[s.src].cycle;
+        int seg = (checkpoint_c > 0 && cyc > 0) ? (cyc - 1) / checkpoint_c : 0;
+        while (cur < seg) { segs.emplace_back(); cur++; }
+        segs[cur].push_back(s);
+    }
+    while (!segs.empty() && segs.back().empty()) segs.pop_back();
+    const int nseg = (int)segs.size();
+    std::vector<std::vector<RTProgram>> progs(nseg);
+    for (int k = 0; k < nseg; k++) {
+        for (const Sweep &sw : regtile_sweeps(segs[k], rq.n, vb)) {
+            progs[k].push_back(build_regtile(segs[k], sw, vb, rq.n));
+            push_regtile(progs[k].back(), rq.n, rq.dtype, OP_REGTILE, &plan->ops, plan);
+        }
+        if (k + 1 < nseg) {
+            Op ck;
+            ck.type = OP_CKPT_STORE;
+            ck.q0 = k;
+            ck.bytes = state_bytes(rq.n, rq.dtype) + state_bytes(rq.n, SV_C64);
+            plan->ops.push_back(ck);
+        }
+    }
+    plan->ncheckpoints = nseg - 1;
+    for (int k = nseg - 1; k >= 0; k--) {
+        for (int i = (int)progs[k].size() - 1; i >= 0; i--)
+            push_regtile(reverse_regtile(progs[k][i]), rq.n, rq.dtype, OP_ADJ_REGTILE, &plan->bops, plan);
+        if (k > 0) {
+            Op ld;
+            ld.type = OP_CKPT_LOAD;
+            ld.q0 = k - 1;
+            ld.bytes = state_bytes(rq.n, rq.dtype) + state_bytes(rq.n, SV_C64);
+            plan->bops.push_back(ld);
+        }
+    }
+    plan->sweeps = (int64_t)(plan->ops.size() + plan->bops.size());
+    plan->bytes = 0;
+    for (const Op &op : plan->ops) plan->bytes += op.bytes;
+    for (const Op &op : plan->bops) plan->bytes += op.bytes;
+    return SV_OK;
+}
+
+}  // namespace svi

@@ -1,0 +1,480 @@
+// Reductions over the output distribution p(x) = |<x|psi>|^2 (Sec. II):
+// probabilities, the one-pass statistics (entropy, uniform cross entropy,
+// normalised moments), the integer-CDF sampler and the sample cross entropy.
+//
+// Everything here is HBM-streaming: one read of the state per statistic
+// pass, at most two for the sampler.  Floating-point sums are formed in
+// FP64 per thread, reduced by fixed shuffle trees inside a workgroup and
+// combined across workgroups in workgroup order with Neumaier's
+// compensated summation, so results are deterministic for a given size.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace svi {
+
+constexpr int RB = 256;   // threads per workgroup
+
+template <typename T> struct cpx { T re, im; };
+
+// p = re*re + im*im with both products and the sum rounded separately (no
+// contraction); for complex64 input both products are exact in FP64.
+__device__ __forceinline__ double prob_of(cpx<float> a) {
+    double r = (double)a.re, i = (double)a.im;
+    return __dadd_rn(__dmul_rn(r, r), __dmul_rn(i, i));
+}
+__device__ __forceinline__ double prob_of(cpx<double> a) {
+    return __dadd_rn(__dmul_rn(a.re, a.re), __dmul_rn(a.im, a.im));
+}
+__device__ __forceinline__ double prob_of(double p) { return p; }
+
+template <typename V>
+__device__ __forceinline__ V wave_sum(V v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Workgroup sum of NV values per thread into red[0..NV) (fixed order).
+template <typename V, int NV>
+__device__ __forceinline__ void block_sum(V (&v)[NV], V *red /* LDS, 4*NV */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; i++) v[i] = wave_sum(v[i]);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; i++) red[wave * NV + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        V s = red[threadIdx.x];
+        for (int w = 1; w < RB / 64; w++) s += red[w * NV + threadIdx.x];
+        red[threadIdx.x] = s;   // each thread reads its column first
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// probabilities
+// ---------------------------------------------------------------------------
+template <typename T, typename O>
+__global__ __launch_bounds__(RB) void k_probs(const cpx<T> *__restrict__ psi, uint64_t begin,
+                                              uint64_t count, O *__restrict__ out) {
+    uint64_t stride = (uint64_t)gridDim.x * RB;
+    for (uint64_t i = (uint64_t)blockIdx.x * RB + threadIdx.x; i < count; i += stride)
+        out[i] = (O)prob_of(psi[begin + i]);
+}
+
+// ---------------------------------------------------------------------------
+// statistics: per workgroup S, sum p ln p, sum ln p, sum u^k (k = 1..10),
+// zero count; u = N p
+// ---------------------------------------------------------------------------
+constexpr int NSTAT = 13;
+
+template <typename T, bool FULL>
+__global__ __launch_bounds__(RB) void k_stats(const cpx<T> *__restrict__ psi, uint64_t chunk,
+                                              double Nd, double *__restrict__ part) {
+    __shared__ double red[4 * NSTAT];
+    __shared__ unsigned long long zred[4];
+    double acc[NSTAT];
+#pragma unroll
+    for (int i = 0; i < NSTAT; i++) acc[i] = 0.0;
+    unsigned long long zeros = 0;
+    const uint64_t start = (uint64_t)blockIdx.x * chunk;
+    for (uint64_t j = start + threadIdx.x; j < start + chunk; j += RB) {
+        const double p = prob_of(psi[j]);
+        acc[0] += p;
+        if (FULL) {
+            if (p > 0.0) {
+                const double l = log(p);
+                acc[1] = fma(p, l, acc[1]);
+                acc[2] += l;
+            } else {
+                zeros++;
+            }
+            const double u = Nd * p;
+            double uk = u;
+#pragma unroll
+            for (int k = 0; k < 10; k++) {
+                acc[3 + k] += uk;
+                uk *= u;
+            }
+        }
+    }
+    block_sum<double, NSTAT>(acc, red);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    zeros = wave_sum(zeros);
+    if (lane == 0) zred[wave] = zeros;
+    __syncthreads();
+    if (threadIdx.x < NSTAT) part[(uint64_t)blockIdx.x * 16 + threadIdx.x] = red[threadIdx.x];
+    if (threadIdx.x == NSTAT) {
+        unsigned long long z = zred[0] + zred[1] + zred[2] + zred[3];
+        part[(uint64_t)blockIdx.x * 16 + NSTAT] = (double)z;
+    }
+}
+
+// Combine per-workgroup partials in workgroup order (Neumaier).
+__global__ void k_combine(const double *__restrict__ part, int nblocks, int nq, double *__restrict__ out) {
+    const int q = threadIdx.x;
+    if (q >= nq) return;
+    double s = 0.0, c = 0.0;
+    for (int b = 0; b < nblocks; b++) {
+        const double x = part[(uint64_t)b * 16 + q];
+        const double t = s + x;
+        if (fabs(s) >= fabs(x)) c += (s - t) + x;
+        else c += (x - t) + s;
+        s = t;
+    }
+    out[q] = s + c;
+}
+
+static void stats_grid(int n, int *nblocks, uint64_t *chunk) {
+    const uint64_t N = 1ull << n;
+    uint64_t nb = N >> 12;
+    if (nb < 1) nb = 1;
+    if (nb > 2048) nb = 2048;
+    *nblocks = (int)nb;
+    *chunk = N / nb;
+}
+
+template <typename T, bool FULL>
+static sv_status stats_typed(sv_state *st, const void *psi, double *host16) {
+    int nb;
+    uint64_t chunk;
+    stats_grid(st->n, &nb, &chunk);
+    SV_TRY(st->ws.reserve((size_t)(nb + 1) * 16 * sizeof(double)));
+    double *part = (double *)st->ws.ptr;
+    double *res = part + (size_t)nb * 16;
+    hipLaunchKernelGGL((k_stats<T, FULL>), dim3(nb), dim3(RB), 0, st->stream, (const cpx<T> *)psi,
+                       chunk, std::ldexp(1.0, st->n), part);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_combine, dim3(1), dim3(64), 0, st->stream, part, nb, FULL ? NSTAT + 1 : 1, res);
+    SV_HIP(hipGetLastError());
+    SV_HIP(hipMemcpyAsync(host16, res, 16 * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+    SV_HIP(hipStreamSynchronize(st->stream));
+    return SV_OK;
+}
+
+sv_status run_stats(sv_state *st, const void *psi, sv_stats *out) {
+    double r[16] = {0};
+    if (st->dt == SV_C64) SV_TRY((stats_typed<float, true>(st, psi, r)));
+    else SV_TRY((stats_typed<double, true>(st, psi, r)));
+    const double N = std::ldexp(1.0, st->n);
+    const double S = r[0];
+    const double lnS = std::log(S);
+    out->norm = S;
+    out->entropy = lnS - r[1] / S;
+    out->zero_count = (int64_t)r[NSTAT];
+    out->unif_ce = out->zero_count ? INFINITY : lnS - r[2] / N;
+    double Sk = 1.0;
+    for (int k = 0; k < 10; k++) {
+        Sk *= S;
+        out->moments[k] = r[3 + k] / N / Sk;
+    }
+    return SV_OK;
+}
+
+// Enqueue the statistics pass of st into res[0..14) without synchronising
+// (used inside captured graphs); part holds up to 2048 partial rows.
+sv_status batch_stats_enqueue(sv_state *st, double *part, double *res) {
+    int nb;
+    uint64_t chunk;
+    stats_grid(st->n, &nb, &chunk);
+    if (st->dt == SV_C64)
+        hipLaunchKernelGGL((k_stats<float, true>), dim3(nb), dim3(RB), 0, st->stream,
+                           (const cpx<float> *)st->data, chunk, std::ldexp(1.0, st->n), part);
+    else
+        hipLaunchKernelGGL((k_stats<double, true>), dim3(nb), dim3(RB), 0, st->stream,
+                           (const cpx<double> *)st->data, chunk, std::ldexp(1.0, st->n), part);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_combine, dim3(1), dim3(64), 0, st->stream, part, nb, NSTAT + 1, res);
+    SV_HIP(hipGetLastError());
+    return SV_OK;
+}
+
+sv_status run_norm(sv_state *st, const void *psi, double *S) {
+    double r[16] = {0};
+    if (st->dt == SV_C64) SV_TRY((stats_typed<float, false>(st, psi, r)));
+    else SV_TRY((stats_typed<double, false>(st, psi, r)));
+    *S = r[0];
+    return SV_OK;
+}
+
+sv_status run_probs(sv_state *st, uint64_t begin, uint64_t count, int f64, void *out) {
+    if (!count) return SV_OK;
+    uint64_t g = (count + RB - 1) / RB;
+    unsigned grid = (unsigned)(g < 16384 ? g : 16384);
+    if (st->dt == SV_C64) {
+        if (f64) hipLaunchKernelGGL((k_probs<float, double>), dim3(grid), dim3(RB), 0, st->stream,
+                                    (const cpx<float> *)st->data, begin, count, (double *)out);
+        else hipLaunchKernelGGL((k_probs<float, float>), dim3(grid), dim3(RB), 0, st->stream,
+                                (const cpx<float> *)st->data, begin, count, (float *)out);
+    } else {
+        if (f64) hipLaunchKernelGGL((k_probs<double, double>), dim3(grid), dim3(RB), 0, st->stream,
+                                    (const cpx<double> *)st->data, begin, count, (double *)out);
+        else hipLaunchKernelGGL((k_probs<double, float>), dim3(grid), dim3(RB), 0, st->stream,
+                                (const cpx<double> *)st->data, begin, count, (float *)out);
+    }
+    SV_HIP(hipGetLastError());
+    return SV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sampler (integer CDF)
+// ---------------------------------------------------------------------------
+// w = floor(p 2^62): the scaling by a power of two is exact and the
+// conversion truncates toward zero.
+__device__ __forceinline__ uint64_t weight_of(double p) {
+    return (uint64_t)(p * 4611686018427387904.0);
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Per bucket of 2^bs entries: W_b = sum of weights (exact integer sum).
+template <typename S>
+__global__ __launch_bounds__(RB) void k_bucket_weights(const S *__restrict__ src, int bs,
+                                                       unsigned long long *__restrict__ bsum) {
+    __shared__ unsigned long long red[4];
+    const uint64_t start = (uint64_t)blockIdx.x << bs;
+    const uint64_t len = 1ull << bs;
+    unsigned long long acc = 0;
+    for (uint64_t j = threadIdx.x; j < len; j += RB) acc += weight_of(prob_of(src[start + j]));
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Exclusive scan of n uint64 values into out[0..n], out[n] = total.  One
+// workgroup of 1024 threads; each thread scans a contiguous stretch.
+__global__ __launch_bounds__(1024) void k_scan(const unsigned long long *__restrict__ in, uint64_t n,
+                                               unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long sh[1024];
+    const uint64_t per = (n + 1023) / 1024;
+    const uint64_t b = threadIdx.x * per;
+    const uint64_t e = b + per < n ? b + per : n;
+    unsigned long long s = 0;
+    for (uint64_t i = b; i < e; i++) s += in[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        unsigned long long v = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : 0ull;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    unsigned long long run = sh[threadIdx.x] - s;   // exclusive prefix of this stretch
+    for (uint64_t i = b; i < e; i++) {
+        out[i] = run;
+        run += in[i];
+    }
+    if (threadIdx.x == 1023) out[n] = sh[1023];
+}
+
+// Per sample: target t = floor(r W / 2^64), its bucket (last b with
+// off[b] <= t) and the target's offset inside the bucket.
+__global__ __launch_bounds__(RB) void k_targets(const uint64_t *__restrict__ words, uint64_t seed,
+                                                int64_t k, const unsigned long long *__restrict__ off,
+                                                uint64_t nb, uint32_t *__restrict__ tb,
+                                                unsigned long long *__restrict__ tloc,
+                                                unsigned long long *__restrict__ counts) {
+    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+    if (i >= k) return;
+    const unsigned long long W = off[nb];
+    const uint64_t r = words ? words[i] : splitmix64(seed, (uint64_t)i);
+    const unsigned long long t = __umul64hi(r, W);
+    uint64_t lo = 0, hi = nb;   // first b with off[b] > t, minus one
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (off[mid] > t) hi = mid; else lo = mid + 1;
+    }
+    const uint64_t b = lo - 1;
+    tb[i] = (uint32_t)b;
+    tloc[i] = t - off[b];
+    atomicAdd(&counts[b], 1ull);
+}
+
+__global__ __launch_bounds__(RB) void k_scatter(int64_t k, const uint32_t *__restrict__ tb,
+                                                const unsigned long long *__restrict__ bstart,
+                                                unsigned long long *__restrict__ cursor,
+                                                uint32_t *__restrict__ bucket) {
+    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+    if (i >= k) return;
+    const uint32_t b = tb[i];
+    const unsigned long long pos = atomicAdd(&cursor[b], 1ull);
+    bucket[bstart[b] + pos] = (uint32_t)i;
+}
+
+// One workgroup per bucket holding samples: prefix sums of the weights by
+// thread stretch, then each sample walks its stretch to the first entry
+// whose running sum exceeds the target (x = min{j : C_j > t}).
+template <typename S>
+__global__ __launch_bounds__(RB) void k_resolve(const S *__restrict__ src, int bs,
+                                                const unsigned long long *__restrict__ counts,
+                                                const unsigned long long *__restrict__ bstart,
+                                                const uint32_t *__restrict__ bucket,
+                                                const unsigned long long *__restrict__ tloc,
+                                                uint64_t *__restrict__ out) {
+    const uint64_t b = blockIdx.x;
+    const unsigned long long cnt = counts[b];
+    if (cnt == 0) return;
+    __shared__ unsigned long long pre[RB + 1];
+    const uint64_t len = 1ull << bs;
+    const uint64_t per = (len + RB - 1) / RB;
+    const uint64_t start = b << bs;
+    const uint64_t lb = threadIdx.x * per;
+    const uint64_t le = lb + per < len ? lb + per : len;
+    unsigned long long s = 0;
+    for (uint64_t j = lb; j < le; j++) s += weight_of(prob_of(src[start + j]));
+    pre[threadIdx.x + 1] = s;
+    if (threadIdx.x == 0) pre[0] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int i = 1; i <= RB; i++) pre[i] += pre[i - 1];
+    __syncthreads();
+    const unsigned long long b0 = bstart[b];
+    for (unsigned long long q = threadIdx.x; q < cnt; q += RB) {
+        const uint32_t smp = bucket[b0 + q];
+        const unsigned long long t = tloc[smp];
+        int lo = 0, hi = RB;   // last stretch with pre[c] <= t
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= t) lo = mid; else hi = mid;
+        }
+        unsigned long long run = pre[lo];
+        const uint64_t jb = (uint64_t)lo * per;
+        const uint64_t je = jb + per < len ? jb + per : len;
+        uint64_t ans = je - 1;
+        for (uint64_t j = jb; j < je; j++) {
+            run += weight_of(prob_of(src[start + j]));
+            if (run > t) { ans = j; break; }
+        }
+        out[smp] = start + ans;
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
+static unsigned cgrid(uint64_t items) {
+    uint64_t g = (items + RB - 1) / RB;
+    return (unsigned)(g < 65535 ? (g ? g : 1) : 65535);
+}
+
+template <typename S>
+static sv_status sample_impl(Workspace *ws, hipStream_t s, const S *src, int n, const uint64_t *words,
+                             uint64_t seed, int64_t k, uint64_t *dev_out) {
+    if (k <= 0) return SV_OK;
+    const int bs = n < 16 ? n : 16;
+    const uint64_t nb = 1ull << (n - bs);
+    size_t need = 0;
+    auto take = [&](size_t bytes) { size_t o = need; need += (bytes + 255) & ~(size_t)255; return o; };
+    size_t o_bsum = take(nb * 8), o_off = take((nb + 1) * 8), o_cnt = take(nb * 8),
+           o_bst = take((nb + 1) * 8), o_cur = take(nb * 8), o_tb = take((size_t)k * 4),
+           o_tl = take((size_t)k * 8), o_bk = take((size_t)k * 4), o_w = take(8);
+    SV_TRY(ws->reserve(need));
+    uint8_t *w = (uint8_t *)ws->ptr;
+    auto *bsum = (unsigned long long *)(w + o_bsum);
+    auto *off = (unsigned long long *)(w + o_off);
+    auto *cnt = (unsigned long long *)(w + o_cnt);
+    auto *bst = (unsigned long long *)(w + o_bst);
+    auto *cur = (unsigned long long *)(w + o_cur);
+    auto *tb = (uint32_t *)(w + o_tb);
+    auto *tl = (unsigned long long *)(w + o_tl);
+    auto *bk = (uint32_t *)(w + o_bk);
+    (void)o_w;
+    hipLaunchKernelGGL((k_bucket_weights<S>), dim3((unsigned)nb), dim3(RB), 0, s, src, bs, bsum);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, bsum, nb, off);
+    unsigned long long W = 0;
+    SV_HIP(hipMemcpyAsync(&W, off + nb, 8, hipMemcpyDeviceToHost, s));
+    SV_HIP(hipStreamSynchronize(s));
+    if (W == 0) return fail(SV_ESTATE, "sampler: every probability rounds to weight 0");
+    hipLaunchKernelGGL(k_zero_u64, dim3(cgrid(nb)), dim3(RB), 0, s, cnt, nb);
+    hipLaunchKernelGGL(k_zero_u64, dim3(cgrid(nb)), dim3(RB), 0, s, cur, nb);
+    const unsigned kg = (unsigned)((k + RB - 1) / RB);
+    hipLaunchKernelGGL(k_targets, dim3(kg), dim3(RB), 0, s, words, seed, k, off, nb, tb, tl, cnt);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, cnt, nb, bst);
+    hipLaunchKernelGGL(k_scatter, dim3(kg), dim3(RB), 0, s, k, tb, bst, cur, bk);
+    hipLaunchKernelGGL((k_resolve<S>), dim3((unsigned)nb), dim3(RB), 0, s, src, bs, cnt, bst, bk, tl,
+                       dev_out);
+    SV_HIP(hipGetLastError());
+    return SV_OK;
+}
+
+sv_status run_sample(sv_state *st, const void *psi, int64_t k, uint64_t seed, uint64_t *dev_out) {
+    if (st->dt == SV_C64)
+        return sample_impl<cpx<float>>(&st->ws, st->stream, (const cpx<float> *)psi, st->n, nullptr,
+                                       seed, k, dev_out);
+    return sample_impl<cpx<double>>(&st->ws, st->stream, (const cpx<double> *)psi, st->n, nullptr,
+                                    seed, k, dev_out);
+}
+
+sv_status run_sample_from(const double *probs, uint64_t N, const uint64_t *r64, int64_t k,
+                          uint64_t *out, hipStream_t s) {
+    int n = 0;
+    while ((1ull << n) < N) n++;
+    if ((1ull << n) != N) return fail(SV_EINVAL, "sv_sample_from: N must be a power of two");
+    // library-owned scratch for this standalone call; kept until the process
+    // ends (never freed from a static destructor, after the runtime is gone)
+    static Workspace *ws = new Workspace();
+    sv_status rc = sample_impl<double>(ws, s, probs, n, r64, 0, k, out);
+    if (rc != SV_OK) return rc;
+    SV_HIP(hipStreamSynchronize(s));
+    return SV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sample cross entropy: sum_i ln p(x_i) and the number of p(x_i) = 0
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(RB) void k_ce(const cpx<T> *__restrict__ psi, uint64_t mask,
+                                           const uint64_t *__restrict__ x, int64_t k, int64_t per,
+                                           double *__restrict__ part) {
+    __shared__ double red[4 * 2];
+    double v[2] = {0.0, 0.0};
+    const int64_t b = (int64_t)blockIdx.x * per;
+    const int64_t e = b + per < k ? b + per : k;
+    for (int64_t i = b + threadIdx.x; i < e; i += RB) {
+        const double p = prob_of(psi[x[i] & mask]);
+        if (p > 0.0) v[0] += log(p);
+        else v[1] += 1.0;
+    }
+    block_sum<double, 2>(v, red);
+    if (threadIdx.x < 2) part[(uint64_t)blockIdx.x * 16 + threadIdx.x] = red[threadIdx.x];
+}
+
+sv_status run_cross_entropy(sv_state *st, const void *psi, const uint64_t *dev_samples, int64_t k,
+                            double S, double *sum_log, int64_t *zeros) {
+    (void)S;
+    if (k <= 0) { *sum_log = 0; *zeros = 0; return SV_OK; }
+    const int64_t per = 4096;
+    const int64_t nb = (k + per - 1) / per;
+    SV_TRY(st->ws.reserve((size_t)(nb + 1) * 16 * sizeof(double)));
+    double *part = (double *)st->ws.ptr;
+    double *res = part + (size_t)nb * 16;
+    const uint64_t mask = (1ull << st->n) - 1;
+    if (st->dt == SV_C64)
+        hipLaunchKernelGGL(k_ce<float>, dim3((unsigned)nb), dim3(RB), 0, st->stream,
+                           (const cpx<float> *)psi, mask, dev_samples, k, per, part);
+    else
+        hipLaunchKernelGGL(k_ce<double>, dim3((unsigned)nb), dim3(RB), 0, st->stream,
+                           (const cpx<double> *)psi, mask, dev_samples, k, per, part);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_combine, dim3(1), dim3(64), 0, st->stream, part, (int)nb, 2, res);
+    double r[2];
+    SV_HIP(hipMemcpyAsync(r, res, 2 * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+    SV_HIP(hipStreamSynchronize(st->stream));
+    *sum_log = r[0];
+    *zeros = (int64_t)r[1];
+    return SV_OK;
+}
+
+}  // namespace svi

@@ -1,0 +1,304 @@
+"""ctypes binding of libsv.so (include/sv.h and include/sv_host.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+library.  Device memory for states comes from PyTorch (a complex tensor on
+the GPU that the library wraps with ``sv_attach``), and work is enqueued on
+PyTorch's current stream.  Importing this module fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsv.so")
+
+SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ERANGE, SV_ESTATE = 0, -1, -2, -3, -4, -5
+C64, C128 = 0, 1
+MODES = {"plain": 0, "spec": 1, "fused": 2, "tiled": 3, "regtile": 4, "auto": 5}
+SWEEP_KINDS = {1: "init", 2: "plain_1q", 3: "plain_cz", 4: "spec_dense", 5: "spec_real",
+               6: "spec_diag", 7: "spec_cz", 8: "regtile", 9: "ldstile", 10: "ldstile_mfma"}
+
+
+class SVError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("sv status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
+                ("cycle", ctypes.c_int32), ("param", ctypes.c_int32), ("mat", ctypes.c_int32)]
+
+
+class CCircuit(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nparams", ctypes.c_int32), ("ngates", ctypes.c_int64),
+                ("gates", ctypes.c_void_p), ("theta", ctypes.c_void_p), ("nmats", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("mats", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("k_max", ctypes.c_int32),
+                ("tile_qubits", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_double), ("entropy", ctypes.c_double),
+                ("unif_ce", ctypes.c_double), ("moments", ctypes.c_double * 10),
+                ("zero_count", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        d = {"norm": self.norm, "entropy": self.entropy, "unif_ce": self.unif_ce,
+             "zero_count": int(self.zero_count)}
+        m = np.array(list(self.moments))
+        for k in range(10):
+            d["M%d" % (k + 1)] = float(m[k])
+        d["moments"] = m
+        return d
+
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "sv_alloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_attach": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p]),
+    "sv_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "sv_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "sv_data": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_apply_circuit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_probs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                ctypes.c_void_p]),
+    "sv_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p,
+                                 ctypes.c_int]),
+    "sv_sample_from": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_cross_entropy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                   ctypes.c_void_p]),
+    "sv_apply_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_last_error": (ctypes.c_char_p, []),
+    "sv_apply_circuit_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_host_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_host_emulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it is missing (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsv.so is not built (run __graft_entry__.build() or "
+                              "python paper_1608_00263_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != SV_OK:
+        raise SVError(status, lib().sv_last_error().decode(errors="replace"))
+
+
+def _ptr(a) -> Optional[int]:
+    return a.ctypes.data if a is not None and a.size else None
+
+
+class CircuitArgs:
+    """Holds an sv_circuit and the arrays it points to."""
+
+    def __init__(self, circ):
+        g = circ.gates
+        self.gates = np.ascontiguousarray(
+            np.stack([g[f] for f in ("kind", "q0", "q1", "cycle", "param", "mat")], axis=1)
+            .astype(np.int32))
+        self.theta = np.ascontiguousarray(circ.theta, dtype=np.float64)
+        self.mats = np.ascontiguousarray(np.asarray(circ.mats, dtype=np.complex128)).view(np.float64)
+        self.c = CCircuit(circ.n, self.theta.size, self.gates.shape[0], _ptr(self.gates),
+                          _ptr(self.theta), self.mats.size // 8, 0, _ptr(self.mats))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+FLAG_FROM_ZERO = 1
+
+
+def make_opts(mode="auto", k_max=0, tile=0, from_zero=False) -> Opts:
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    return Opts(m, k_max, tile, FLAG_FROM_ZERO if from_zero else 0)
+
+
+def _stream_handle(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class State:
+    """A 2^n state on the GPU: a torch tensor wrapped by an sv_state handle."""
+
+    def __init__(self, n: int, dtype: str = "c64", device: str = "cuda:0", tensor=None):
+        import torch
+        self.torch = torch
+        self.n = n
+        self.dt = C64 if dtype == "c64" else C128
+        tdt = torch.complex64 if self.dt == C64 else torch.complex128
+        if tensor is None:
+            tensor = torch.zeros(1 << n, dtype=tdt, device=device)
+        assert tensor.dtype == tdt and tensor.numel() == (1 << n) and tensor.is_contiguous()
+        self.tensor = tensor
+        h = ctypes.c_void_p()
+        check(lib().sv_attach(n, self.dt, ctypes.c_void_p(tensor.data_ptr()),
+                              _stream_handle(torch), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sv_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self):
+        check(lib().sv_reset(self.h))
+
+    def apply(self, circ, mode="auto", k_max=0, tile=0, args: Optional[CircuitArgs] = None,
+              from_zero=False):
+        """Apply circ in place (from |0..0> regardless of contents if from_zero)."""
+        a = args or CircuitArgs(circ)
+        o = make_opts(mode, k_max, tile, from_zero)
+        check(lib().sv_apply_circuit(self.h, a.ref, ctypes.byref(o)))
+
+    def apply_timed(self, circ, mode="auto", k_max=0, tile=0, args: Optional[CircuitArgs] = None,
+                    from_zero=False):
+        """Apply with per-sweep HIP event timing; returns (ms, kinds, bytes) arrays."""
+        a = args or CircuitArgs(circ)
+        o = make_opts(mode, k_max, tile, from_zero)
+        cap = 4096
+        ms = np.zeros(cap, dtype=np.float32)
+        kinds = np.zeros(cap, dtype=np.int32)
+        by = np.zeros(cap, dtype=np.float64)
+        n = ctypes.c_int64()
+        check(lib().sv_apply_circuit_timed(self.h, a.ref, ctypes.byref(o), cap, _ptr(ms), _ptr(kinds),
+                                           _ptr(by), ctypes.byref(n)))
+        m = min(n.value, cap)
+        return ms[:m], kinds[:m], by[:m]
+
+    def plan_info(self, circ, mode="auto", k_max=0, tile=0):
+        a = CircuitArgs(circ)
+        o = make_opts(mode, k_max, tile)
+        sw = ctypes.c_int64()
+        by = ctypes.c_double()
+        check(lib().sv_plan_info(self.h, a.ref, ctypes.byref(o), ctypes.byref(sw), ctypes.byref(by)))
+        return sw.value, by.value
+
+    def amplitudes(self) -> np.ndarray:
+        self.torch.cuda.synchronize()
+        return self.tensor.cpu().numpy()
+
+    def probs(self, begin: int = 0, count: Optional[int] = None, f64: bool = True):
+        torch = self.torch
+        count = (1 << self.n) - begin if count is None else count
+        out = torch.empty(max(count, 1), dtype=torch.float64 if f64 else torch.float32,
+                          device=self.tensor.device)
+        check(lib().sv_probs(self.h, begin, count, 1 if f64 else 0, ctypes.c_void_p(out.data_ptr())))
+        return out[:count]
+
+    def moments(self) -> dict:
+        s = Stats()
+        check(lib().sv_moments(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def sample(self, k: int, seed: int) -> np.ndarray:
+        out = np.zeros(max(k, 1), dtype=np.uint64)
+        check(lib().sv_sample(self.h, k, ctypes.c_uint64(seed), _ptr(out), 0))
+        return out[:k]
+
+    def cross_entropy(self, samples: np.ndarray):
+        x = np.ascontiguousarray(samples, dtype=np.uint64)
+        ce = ctypes.c_double()
+        dh = ctypes.c_double()
+        z = ctypes.c_int64()
+        check(lib().sv_cross_entropy(self.h, _ptr(x), x.size, ctypes.byref(ce), ctypes.byref(dh),
+                                     ctypes.byref(z)))
+        return ce.value, dh.value, z.value
+
+    def backward(self, circ, samples: np.ndarray, checkpoint_c: int = 0, mode="auto", k_max=0,
+                 tile=0):
+        a = CircuitArgs(circ)
+        o = make_opts(mode, k_max, tile)
+        x = np.ascontiguousarray(samples, dtype=np.uint64)
+        grad = np.zeros(max(circ.nparams, 1))
+        loss = ctypes.c_double()
+        check(lib().sv_backward(self.h, a.ref, ctypes.byref(o), _ptr(x), x.size, checkpoint_c,
+                                ctypes.byref(loss), _ptr(grad)))
+        return loss.value, grad[:circ.nparams]
+
+
+def sample_from(probs, words, torch=None):
+    """Sampler on an explicit distribution (device tensors in, device out)."""
+    import torch as _t
+    torch = torch or _t
+    out = torch.empty(max(words.numel(), 1), dtype=torch.int64, device=probs.device)
+    check(lib().sv_sample_from(ctypes.c_void_p(probs.data_ptr()), probs.numel(),
+                               ctypes.c_void_p(words.data_ptr()), words.numel(),
+                               ctypes.c_void_p(out.data_ptr()), _stream_handle(torch)))
+    return out[:words.numel()]
+
+
+def apply_batch(states, circuits, mode="auto", k_max=0, tile=0):
+    """Simulate each circuit from |0..0> into its state; returns per-instance stats."""
+    args = [CircuitArgs(c) for c in circuits]
+    arr = (CCircuit * len(args))(*[a.c for a in args])
+    hs = (ctypes.c_void_p * len(states))(*[s.h.value for s in states])
+    out = (Stats * len(states))()
+    o = make_opts(mode, k_max, tile)
+    check(lib().sv_apply_batch(hs, arr, len(states), ctypes.byref(o), out))
+    return [s.as_dict() for s in out]
+
+
+# ---- host-only diagnostics (no GPU) -----------------------------------------
+def host_plan(circ, dtype="c64", mode="auto", k_max=0, tile=0, from_zero=True):
+    a = CircuitArgs(circ)
+    o = make_opts(mode, k_max, tile)
+    sw = ctypes.c_int64()
+    by = ctypes.c_double()
+    mf = ctypes.c_int64()
+    check(lib().sv_host_plan(a.ref, C64 if dtype == "c64" else C128, ctypes.byref(o),
+                             1 if from_zero else 0, ctypes.byref(sw), ctypes.byref(by),
+                             ctypes.byref(mf)))
+    return {"sweeps": sw.value, "bytes": by.value, "mfma_sweeps": mf.value}
+
+
+def host_emulate(circ, psi: np.ndarray, dtype="c64", mode="auto", k_max=0, tile=0,
+                 from_zero=True) -> np.ndarray:
+    a = CircuitArgs(circ)
+    o = make_opts(mode, k_max, tile)
+    psi = np.ascontiguousarray(psi, dtype=np.complex128).copy()
+    check(lib().sv_host_emulate(a.ref, C64 if dtype == "c64" else C128, ctypes.byref(o),
+                                1 if from_zero else 0, _ptr(psi)))
+    return psi

@@ -1,0 +1,225 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 reference.
+
+Tolerances (stated by the target of the work, here written out):
+  amplitudes  ||psi_gpu - psi_ref||_2 <= 1e-4 (complex64), <= 1e-11 (complex128)
+  cross entropy / entropy  within 1e-4 nats
+  sampler     bit-exact on identical probabilities and random words
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_00263_amd import circuits as C
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1608_00263_amd import sv  # noqa: E402  (fails loudly if libsv.so is missing)
+
+TOL = {"c64": 1e-4, "c128": 1e-11}
+MODES = [("plain", 0, 0), ("spec", 0, 0), ("regtile", 0, 0), ("regtile", 0, 3), ("regtile", 0, 6),
+         ("fused", 2, 0), ("fused", 3, 0), ("fused", 4, 0), ("fused", 5, 0), ("tiled", 3, 10),
+         ("tiled", 4, 12), ("tiled", 5, 13)]
+
+
+def run_gpu(circ, dtype, mode, k, t, psi0=None):
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    if psi0 is None:
+        st = sv.State(circ.n, dtype)
+        st.reset()
+    else:
+        st = sv.State(circ.n, dtype, tensor=torch.from_numpy(psi0.astype(
+            np.complex64 if dtype == "c64" else np.complex128)).to("cuda"))
+    st.apply(circ, mode, k, t)
+    out = st.amplitudes().astype(np.complex128)
+    st.close()
+    assert out.dtype == np.complex128 and tdt is not None
+    return out
+
+
+@pytest.fixture(scope="module")
+def c1():
+    circ = C.make_circuit(4, 4, 25, seed=1)
+    return circ, oracle.apply_circuit(circ)
+
+
+@pytest.mark.parametrize("mode,k,t", MODES)
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_c1_amplitudes(c1, mode, k, t, dtype):
+    circ, ref = c1
+    if dtype == "c128" and t == 13:
+        t = 12
+    if dtype == "c128" and mode == "regtile" and t == 6:
+        t = 5
+    out = run_gpu(circ, dtype, mode, k, t)
+    assert np.linalg.norm(out - ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("mode,k,t", MODES)
+def test_random_kinds_from_random_state(mode, k, t):
+    # all gate kinds, dense U1 gates, CZ on arbitrary pairs, arbitrary start
+    n = 13
+    circ = C.random_unitary_circuit(n, 220, seed=5)
+    psi0 = C.random_state(n, 6, dtype=np.complex128)
+    ref = oracle.apply_circuit(circ, psi0.copy())
+    out = run_gpu(circ, "c128", mode, k, min(t, 12), psi0=psi0)
+    assert np.linalg.norm(out - ref) <= TOL["c128"]
+    out = run_gpu(circ, "c64", mode, k, t, psi0=psi0)
+    assert np.linalg.norm(out - ref) <= TOL["c64"]
+
+
+@pytest.mark.parametrize("n", [10, 11, 17, 22])
+def test_sizes_and_tiles(n):
+    # sizes from the smallest tiled case up to many tiles per sweep
+    rows, cols = {10: (2, 5), 11: (1, 11), 17: (1, 17), 22: (2, 11)}[n]
+    circ = C.make_circuit(rows, cols, 24, seed=n)
+    ref = oracle.apply_circuit(circ)
+    for mode, k, t in [("regtile", 0, 0), ("fused", 4, 0), ("tiled", 5, 12), ("spec", 0, 0)]:
+        out = run_gpu(circ, "c64", mode, k, t)
+        assert np.linalg.norm(out - ref) <= TOL["c64"], (mode, k, t)
+
+
+def test_grid_24q_depth40():
+    circ = C.make_circuit(4, 6, 40, seed=24)
+    ref = oracle.apply_circuit(circ)
+    for mode, k, t in [("regtile", 0, 5), ("regtile", 0, 6), ("fused", 5, 0), ("tiled", 4, 13)]:
+        out = run_gpu(circ, "c64", mode, k, t)
+        assert np.linalg.norm(out - ref) <= TOL["c64"], (mode, k, t)
+    out = run_gpu(circ, "c128", "regtile", 0, 5)
+    assert np.linalg.norm(out - ref) <= TOL["c128"]
+
+
+# ---------------------------------------------------------------------------
+# statistics, probabilities
+# ---------------------------------------------------------------------------
+def test_probs_exact_and_ranges():
+    n = 14
+    psi = C.random_state(n, 11, dtype=np.complex64)
+    st = sv.State(n, "c64", tensor=torch.from_numpy(psi).to("cuda"))
+    p = st.probs().cpu().numpy()
+    np.testing.assert_array_equal(p, oracle.probs(psi))     # exact products, one rounding
+    part = st.probs(1000, 77).cpu().numpy()
+    np.testing.assert_array_equal(part, oracle.probs(psi)[1000:1077])
+    with pytest.raises(sv.SVError) as e:
+        st.probs(1 << n, 1)
+    assert e.value.status == sv.SV_ERANGE
+    st.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_moments_identical_input(dtype):
+    n = 18
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    psi = C.random_state(n, 12, dtype=npdt)
+    st = sv.State(n, dtype, tensor=torch.from_numpy(psi).to("cuda"))
+    got = st.moments()
+    want = oracle.stats(oracle.probs(psi))
+    for key in ("norm", "entropy", "unif_ce"):
+        assert abs(got[key] - want[key]) <= 1e-12 * max(1, abs(want[key])), key
+    np.testing.assert_allclose(got["moments"], want["moments"], rtol=1e-11)
+    assert got["zero_count"] == 0
+    st.close()
+
+
+def test_moments_edge_cases():
+    n = 12
+    st = sv.State(n, "c64")
+    st.reset()                               # point mass
+    m = st.moments()
+    assert m["entropy"] == 0.0 and m["zero_count"] == (1 << n) - 1 and math.isinf(m["unif_ce"])
+    np.testing.assert_allclose(m["moments"], [float(1 << n) ** (k - 1) for k in range(1, 11)],
+                               rtol=1e-12)
+    st.close()
+
+
+def test_c1_statistics_and_ce(c1):
+    circ, ref = c1
+    want = oracle.stats(oracle.probs(ref))
+    st = sv.State(circ.n, "c64")
+    st.reset()
+    st.apply(circ, "regtile")
+    got = st.moments()
+    for key in ("entropy", "unif_ce"):
+        assert abs(got[key] - want[key]) <= 1e-4
+    np.testing.assert_allclose(got["moments"][:6], want["moments"][:6], rtol=1e-3)
+    xs = oracle.sample(oracle.probs(ref), 10000, 1001)
+    ce, dh, z = st.cross_entropy(xs)
+    ce0, dh0, z0 = oracle.cross_entropy(oracle.probs(ref), xs)
+    assert abs(ce - ce0) <= 1e-4 and abs(dh - dh0) <= 1e-4 and z == z0 == 0
+    st.close()
+
+
+# ---------------------------------------------------------------------------
+# sampler: bit-exact
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,zeros,k", [(4, 0, 1), (12, 7, 5000), (17, 1000, 20000), (20, 0, 100000)])
+def test_sample_from_bit_exact(n, zeros, k):
+    p = C.random_probabilities(1 << n, 30 + n, zeros=zeros)
+    words = C.splitmix64_words(50 + n, k)
+    want = oracle.sample_from_words(p, words)
+    got = sv.sample_from(torch.from_numpy(p).to("cuda"),
+                         torch.from_numpy(words.view(np.int64)).to("cuda")).cpu().numpy()
+    np.testing.assert_array_equal(got.view(np.uint64), want)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_sample_state_bit_exact(dtype):
+    n = 19
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    psi = C.random_state(n, 40, dtype=npdt)
+    st = sv.State(n, dtype, tensor=torch.from_numpy(psi).to("cuda"))
+    got = st.sample(30000, 1234)
+    want = oracle.sample(oracle.probs(psi), 30000, 1234)
+    np.testing.assert_array_equal(got, want)
+    assert st.sample(0, 1).size == 0
+    st.close()
+
+
+def test_sample_point_mass():
+    st = sv.State(10, "c64")
+    st.reset()
+    assert (st.sample(100, 7) == 0).all()
+    st.close()
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,ck", [("c128", 0), ("c128", 3), ("c64", 0), ("c64", 4)])
+def test_adjoint_vs_oracle(dtype, ck):
+    circ = C.make_circuit(3, 4, 14, seed=61, parametrise=True, theta_seed=62, theta_std=0.05)
+    p0 = oracle.probs(oracle.apply_circuit(circ.with_theta(np.zeros(circ.nparams))))
+    xs = oracle.sample(p0, 2000, 1004)
+    loss0, g0 = oracle.adjoint(circ, xs)
+    st = sv.State(circ.n, dtype)
+    loss, g = st.backward(circ, xs, checkpoint_c=ck)
+    st.close()
+    if dtype == "c128":
+        assert abs(loss - loss0) < 1e-9
+        assert np.abs(g - g0).max() < 1e-9
+    else:
+        assert abs(loss - loss0) < 1e-4
+        assert np.abs(g - g0).max() < 1e-4
+        assert np.linalg.norm(g - g0) <= 1e-3 * np.linalg.norm(g0)
+
+
+# ---------------------------------------------------------------------------
+# ensemble
+# ---------------------------------------------------------------------------
+def test_batch_matches_oracle():
+    circs = [C.make_circuit(r, c, d, seed=300 + i)
+             for i, (r, c, d) in enumerate([(2, 5, 12), (3, 4, 20), (2, 6, 15), (3, 4, 9)])]
+    states = [sv.State(c.n, "c64") for c in circs]
+    res = sv.apply_batch(states, circs)
+    for c, st, r in zip(circs, states, res):
+        ref = oracle.apply_circuit(c)
+        want = oracle.stats(oracle.probs(ref))
+        assert abs(r["entropy"] - want["entropy"]) < 1e-4
+        np.testing.assert_allclose(r["moments"][:5], want["moments"][:5], rtol=1e-3)
+        assert np.linalg.norm(st.amplitudes() - ref) < 1e-4
+        st.close()
