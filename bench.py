@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="regtile")
-    ap.add_argument("--tile", type=int, default=6)
+    ap.add_argument("--tile", type=int, default=5)
     ap.add_argument("--samples", type=int, default=100000)
     ap.add_argument("--no-modes", action="store_true", help="skip the per-mode circuit timings")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint timing")

@@ -206,11 +206,16 @@ sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k,
 
 /* Gradient of L(theta) = -(1/k) sum_i ln p_theta(x_i) with respect to
  * theta (length c->nparams, host), by the adjoint method: the forward state
- * is rebuilt by applying the inverse gates (no stored history), with a
- * single-precision copy of the forward state kept at the end of every
- * checkpoint_c-th cycle (0 = none) and reloaded on the way back.  On entry
- * the handle may hold anything; on return it holds U(theta)|0>.  loss gets
- * L(theta).  SV_EINVAL if a parametrised gate is not a rotation. */
+ * is rebuilt by applying the inverse gates (no stored history), with a copy
+ * of the forward state in the state's precision (complex64 on the bulk
+ * path) kept at the end of every checkpoint_c-th cycle (0 = none) and
+ * reloaded on the way back.  The circuit must open with a Hadamard on every
+ * qubit and list its gates in nondecreasing cycle order.  On entry the
+ * handle may hold anything; on return its contents are unspecified (the
+ * forward state has been uncomputed).  loss gets L(theta).  Uses device
+ * scratch of one extra state plus the checkpoints.  SV_EINVAL if a
+ * parametrised gate is not a rotation; SV_ESTATE if a sample has p = 0;
+ * SV_ERANGE for n < 8. */
 sv_status sv_backward(sv_state *st, const sv_circuit *c, const sv_opts *opts,
                       const uint64_t *samples, int64_t k, int checkpoint_c,
                       double *loss, double *grad);

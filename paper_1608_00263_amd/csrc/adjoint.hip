@@ -5,9 +5,9 @@
 // lambda_x = n_x psi_x / (m p_x) and dU_g = D_g U_g, walking the gates
 // backwards from phi = psi, mu = lambda gives
 //     dL/dtheta_g = -2 Re <mu| D_g |phi>,   then phi <- U_g^dag phi, mu <- U_g^dag mu.
-// phi is rebuilt by applying inverse gates rather than stored; a
-// complex64 copy of the forward state at every checkpoint bounds the
-// drift of that uncomputation.
+// phi is rebuilt by applying inverse gates rather than stored; a copy of
+// the forward state at every checkpoint (complex64 for the complex64 path)
+// bounds the drift of that uncomputation.
 //
 // The backward sweeps reuse the register tiles of the forward plan with
 // the programs reversed and conjugated, carrying phi and mu through the
@@ -220,18 +220,6 @@ __global__ __launch_bounds__(BLOCK) void k_zero(cplx<T> *__restrict__ v, uint64_
     }
 }
 
-template <typename A, typename B>
-__global__ __launch_bounds__(BLOCK) void k_convert(const cplx<A> *__restrict__ src, cplx<B> *__restrict__ dst,
-                                                   uint64_t N) {
-    uint64_t stride = (uint64_t)gridDim.x * BLOCK;
-    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < N; i += stride) {
-        cplx<B> o;
-        o.re = (B)src[i].re;
-        o.im = (B)src[i].im;
-        dst[i] = o;
-    }
-}
-
 // gradient slot s = -2 sum over tiles of gpart[tile][s], tiles in order
 // (Neumaier)
 __global__ void k_grad_reduce(const double *__restrict__ gpart, uint64_t ntiles, int nslots,
@@ -269,7 +257,10 @@ static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *
     const uint64_t ntiles = vb ? N >> (LANE_BITS + vb) : 0;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t b_mu = al(N * sizeof(cplx<T>));
-    const size_t b_ck = al(N * sizeof(cplx<float>)) * (size_t)plan.ncheckpoints;
+    // checkpoints: complex64 (the state's own precision for complex64; a
+    // complex128 state keeps complex128 copies so that reloading them costs
+    // no accuracy)
+    const size_t b_ck = al(N * sizeof(cplx<T>)) * (size_t)plan.ncheckpoints;
     const size_t b_x = al((size_t)k * 8);
     const size_t b_gp = al((size_t)ntiles * (nslots ? nslots : 1) * 8);
     const size_t b_gs = al((size_t)(nslots ? nslots : 1) * 8);
@@ -281,15 +272,12 @@ static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *
     double *gpart = (double *)((uint8_t *)dx + b_x);
     double *gsum = (double *)((uint8_t *)gpart + b_gp);
     cplx<T> *phi = (cplx<T> *)st->data;
-    auto ckpt = [&](int i) { return (cplx<float> *)(ck + (size_t)i * al(N * sizeof(cplx<float>))); };
+    auto ckpt = [&](int i) { return (cplx<T> *)(ck + (size_t)i * al(N * sizeof(cplx<T>))); };
 
     // forward pass from |0..0>, storing checkpoints
     for (const Op &op : plan.ops) {
         if (op.type == OP_CKPT_STORE) {
-            if (sizeof(T) == 4)
-                SV_HIP(hipMemcpyAsync(ckpt(op.q0), phi, N * sizeof(cplx<float>), hipMemcpyDeviceToDevice, s));
-            else
-                hipLaunchKernelGGL((k_convert<T, float>), dim3(ggrid(N)), dim3(BLOCK), 0, s, phi, ckpt(op.q0), N);
+            SV_HIP(hipMemcpyAsync(ckpt(op.q0), phi, N * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
         } else {
             SV_TRY(launch_op(st, plan, op, phi));
         }
@@ -309,10 +297,7 @@ static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *
     // backward sweeps
     for (const Op &op : plan.bops) {
         if (op.type == OP_CKPT_LOAD) {
-            if (sizeof(T) == 4)
-                SV_HIP(hipMemcpyAsync(phi, ckpt(op.q0), N * sizeof(cplx<float>), hipMemcpyDeviceToDevice, s));
-            else
-                hipLaunchKernelGGL((k_convert<float, T>), dim3(ggrid(N)), dim3(BLOCK), 0, s, ckpt(op.q0), phi, N);
+            SV_HIP(hipMemcpyAsync(phi, ckpt(op.q0), N * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
             continue;
         }
         const uint8_t *prog = (const uint8_t *)plan.dprog + op.prog_off;

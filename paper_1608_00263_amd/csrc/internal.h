@@ -151,7 +151,7 @@ enum OpType : int32_t {
     OP_REGTILE,             // register-tile program
     OP_LDSTILE,             // LDS-tile program
     OP_ADJ_REGTILE,         // adjoint register-tile program (phi and mu)
-    OP_CKPT_STORE,          // copy the state to checkpoint q0 (complex64)
+    OP_CKPT_STORE,          // copy the state to checkpoint q0
     OP_CKPT_LOAD,           // overwrite the state with checkpoint q0
 };
 

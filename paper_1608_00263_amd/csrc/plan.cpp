@@ -857,7 +857,7 @@ sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int che
             Op ck;
             ck.type = OP_CKPT_STORE;
             ck.q0 = k;
-            ck.bytes = state_bytes(rq.n, rq.dtype) + state_bytes(rq.n, SV_C64);
+            ck.bytes = 2 * state_bytes(rq.n, rq.dtype);
             plan->ops.push_back(ck);
         }
     }
@@ -869,7 +869,7 @@ sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int che
             Op ld;
             ld.type = OP_CKPT_LOAD;
             ld.q0 = k - 1;
-            ld.bytes = state_bytes(rq.n, rq.dtype) + state_bytes(rq.n, SV_C64);
+            ld.bytes = 2 * state_bytes(rq.n, rq.dtype);
             plan->bops.push_back(ld);
         }
     }
