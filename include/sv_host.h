@@ -32,6 +32,12 @@ sv_status sv_host_plan(const sv_circuit *c, sv_dtype dt, const sv_opts *opts, in
 sv_status sv_host_emulate(const sv_circuit *c, sv_dtype dt, const sv_opts *opts, int from_zero,
                           double *psi);
 
+/* Text description of that plan, one line per sweep (kind, tile qubits,
+ * gate and term counts), written to buf (NUL-terminated, at most cap
+ * bytes, truncated if longer). */
+sv_status sv_host_plan_describe(const sv_circuit *c, sv_dtype dt, const sv_opts *opts, int from_zero,
+                                char *buf, int64_t cap);
+
 #ifdef __cplusplus
 }
 #endif

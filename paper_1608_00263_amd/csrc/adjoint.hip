@@ -76,8 +76,8 @@ __device__ __forceinline__ double grad_lane(const cplx<T> (&phi)[NR], const cplx
 #pragma unroll
     for (int r = 0; r < NR; r++) {
         cplx<T> p;
-        p.re = lane_xor(phi[r].re, 1 << B);
-        p.im = lane_xor(phi[r].im, 1 << B);
+        p.re = lane_xor<B>(phi[r].re);
+        p.im = lane_xor<B>(phi[r].im);
         acc += re_conj_mul(mu[r], cmad(cp, p, cmul(cs, phi[r])));
     }
     return acc;
@@ -137,12 +137,13 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
                 if (lane == 0) gpart[tile * (uint64_t)nslots + slot] = g;
             }
             const Mat2<T> u = load_mat<T>(ops[o].u);
+            const int form = ops[o].form;
             if (kind == RT_REG) {
-                reg_gate_dispatch<T, NR>(phi, u, arg);
-                reg_gate_dispatch<T, NR>(mu, u, arg);
+                reg_gate_dispatch<T, NR>(phi, u, arg, form);
+                reg_gate_dispatch<T, NR>(mu, u, arg, form);
             } else {
-                lane_gate_dispatch<T, NR>(phi, u, arg, lane);
-                lane_gate_dispatch<T, NR>(mu, u, arg, lane);
+                lane_gate_dispatch<T, NR>(phi, u, arg, lane, form);
+                lane_gate_dispatch<T, NR>(mu, u, arg, lane, form);
             }
         } else if (kind == RT_SIGNS) {
             uint64_t par = 0;
@@ -220,15 +221,30 @@ __global__ __launch_bounds__(BLOCK) void k_zero(cplx<T> *__restrict__ v, uint64_
     }
 }
 
-// gradient slot s = -2 sum over tiles of gpart[tile][s], tiles in order
-// (Neumaier)
-__global__ void k_grad_reduce(const double *__restrict__ gpart, uint64_t ntiles, int nslots,
-                              double *__restrict__ out) {
+// Gradient slot sums, two levels in a fixed order: chunk c of 256 tiles is
+// summed serially per slot (threads over slots, coalesced rows), then the
+// chunk partials are combined in chunk order with Neumaier's summation and
+// scaled by -2.
+constexpr int GCHUNK = 256;
+
+__global__ __launch_bounds__(256) void k_grad_partial(const double *__restrict__ gpart, uint64_t ntiles,
+                                                      int nslots, double *__restrict__ part) {
+    const uint64_t t0 = (uint64_t)blockIdx.x * GCHUNK;
+    const uint64_t t1 = t0 + GCHUNK < ntiles ? t0 + GCHUNK : ntiles;
+    for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
+        double acc = 0;
+        for (uint64_t t = t0; t < t1; t++) acc += gpart[t * (uint64_t)nslots + s];
+        part[(uint64_t)blockIdx.x * nslots + s] = acc;
+    }
+}
+
+__global__ void k_grad_final(const double *__restrict__ part, uint64_t nchunks, int nslots,
+                             double *__restrict__ out) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nslots) return;
     double sum = 0, c = 0;
-    for (uint64_t t = 0; t < ntiles; t++) {
-        const double x = gpart[t * (uint64_t)nslots + s];
+    for (uint64_t b = 0; b < nchunks; b++) {
+        const double x = part[b * (uint64_t)nslots + s];
         const double u = sum + x;
         if (fabs(sum) >= fabs(x)) c += (sum - u) + x;
         else c += (x - u) + sum;
@@ -263,7 +279,8 @@ static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *
     const size_t b_ck = al(N * sizeof(cplx<T>)) * (size_t)plan.ncheckpoints;
     const size_t b_x = al((size_t)k * 8);
     const size_t b_gp = al((size_t)ntiles * (nslots ? nslots : 1) * 8);
-    const size_t b_gs = al((size_t)(nslots ? nslots : 1) * 8);
+    const uint64_t nchunks = (ntiles + GCHUNK - 1) / GCHUNK;
+    const size_t b_gs = al((size_t)(nslots ? nslots : 1) * 8 * (nchunks + 1));
     SV_TRY(st->ws2.reserve(b_mu + b_ck + b_x + b_gp + b_gs));
     uint8_t *w = (uint8_t *)st->ws2.ptr;
     cplx<T> *mu = (cplx<T> *)w;
@@ -316,7 +333,10 @@ static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *
     }
     std::vector<double> slots(nslots);
     if (nslots) {
-        hipLaunchKernelGGL(k_grad_reduce, dim3((nslots + 255) / 256), dim3(256), 0, s, gpart, ntiles, nslots,
+        double *gchunk = gsum + nslots;
+        hipLaunchKernelGGL(k_grad_partial, dim3((unsigned)nchunks), dim3(256), 0, s, gpart, ntiles, nslots,
+                           gchunk);
+        hipLaunchKernelGGL(k_grad_final, dim3((nslots + 255) / 256), dim3(256), 0, s, gchunk, nchunks, nslots,
                            gsum);
         SV_HIP(hipGetLastError());
         SV_HIP(hipMemcpyAsync(slots.data(), gsum, nslots * 8, hipMemcpyDeviceToHost, s));

@@ -1,7 +1,10 @@
 // Host replay of sweep plans (include/sv_host.h): interprets the tile
 // programs byte for byte as the GPU kernels do, in double precision.
+#include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <string>
 #include <vector>
 
 #include "../../include/sv_host.h"
@@ -38,6 +41,17 @@ static void emulate_regtile(const Plan &plan, const Op &op, int n, cx *psi) {
             const RTOp &p = ops[o];
             cx u[4];
             for (int i = 0; i < 4; i++) u[i] = rnd(to_cx(p.u, i));
+            // the add-only forms are sqrt2 times the gate
+            const cx I(0, 1);
+            switch (p.form) {
+            case F_H: u[0] = 1; u[1] = 1; u[2] = 1; u[3] = -1; break;
+            case F_SX: u[0] = 1; u[1] = -I; u[2] = -I; u[3] = 1; break;
+            case F_SY: u[0] = 1; u[1] = -1; u[2] = 1; u[3] = 1; break;
+            case F_SXDG: u[0] = 1; u[1] = I; u[2] = I; u[3] = 1; break;
+            case F_SYDG: u[0] = 1; u[1] = 1; u[2] = -1; u[3] = 1; break;
+            case F_PHASE: u[0] = 1; u[1] = 0; u[2] = 0; break;
+            default: break;
+            }
             if (p.kind == RT_REG) {
                 for (int l = 0; l < 64; l++)
                     for (int r = 0; r < nr; r++) {
@@ -79,8 +93,9 @@ static void emulate_regtile(const Plan &plan, const Op &op, int n, cx *psi) {
                 }
             }
         }
+        const double sc = std::ldexp(1.0, h->sexp) * (h->shalf ? 1.0 / std::sqrt(2.0) : 1.0);
         for (int l = 0; l < 64; l++)
-            for (int r = 0; r < nr; r++) psi[base + roff[r] + l] = a[l * nr + r];
+            for (int r = 0; r < nr; r++) psi[base + roff[r] + l] = a[l * nr + r] * sc;
     }
 }
 
@@ -238,5 +253,51 @@ extern "C" sv_status sv_host_emulate(const sv_circuit *c, sv_dtype dt, const sv_
     Plan plan;
     SV_TRY(host_plan(c, dt, opts, from_zero, &plan));
     for (const Op &op : plan.ops) emulate_op(plan, op, c->n, (cx *)psi);
+    return SV_OK;
+}
+
+extern "C" sv_status sv_host_plan_describe(const sv_circuit *c, sv_dtype dt, const sv_opts *opts,
+                                           int from_zero, char *buf, int64_t cap) {
+    Plan plan;
+    SV_TRY(host_plan(c, dt, opts, from_zero, &plan));
+    std::string out;
+    char line[256];
+    for (size_t i = 0; i < plan.ops.size(); i++) {
+        const Op &op = plan.ops[i];
+        if (op.type == OP_REGTILE) {
+            const RTHeader *h = (const RTHeader *)(plan.prog.data() + op.prog_off);
+            const RTOp *ops = (const RTOp *)((const uint8_t *)h + h->op_off);
+            int nreg = 0, nlane = 0, nsign = 0, nterm = 0, nphase = 0;
+            for (int o = 0; o < h->nops; o++) {
+                if (ops[o].kind == RT_REG) nreg++;
+                else if (ops[o].kind == RT_LANE) nlane++;
+                else if (ops[o].kind == RT_SIGNS) { nsign++; nterm += ops[o].nterms; }
+                else nphase++;
+            }
+            std::string rq;
+            for (int j = 0; j < h->vbits; j++) rq += (j ? "," : "") + std::to_string(h->rq[j]);
+            snprintf(line, sizeof line, "%zu regtile v=%d rq=[%s] reg=%d lane=%d signops=%d cz=%d phase=%d\n", i,
+                     h->vbits, rq.c_str(), nreg, nlane, nsign, nterm, nphase);
+        } else if (op.type == OP_LDSTILE) {
+            const LTHeader *h = (const LTHeader *)(plan.prog.data() + op.prog_off);
+            const LTOp *ops = (const LTOp *)((const uint8_t *)h + h->op_off);
+            std::string ks;
+            int nd = 0;
+            for (int o = 0; o < h->nops; o++) {
+                if (ops[o].kind == LT_BLOCK) ks += std::to_string(ops[o].k);
+                else nd += ops[o].nterms;
+            }
+            snprintf(line, sizeof line, "%zu ldstile m=%d blocks=[%s] diagterms=%d mfma=%d\n", i, h->mbits,
+                     ks.c_str(), nd, op.mfma);
+        } else {
+            snprintf(line, sizeof line, "%zu op%d q0=%d q1=%d\n", i, (int)op.type, op.q0, op.q1);
+        }
+        out += line;
+    }
+    if (buf && cap > 0) {
+        size_t m = std::min((size_t)cap - 1, out.size());
+        memcpy(buf, out.data(), m);
+        buf[m] = 0;
+    }
     return SV_OK;
 }

@@ -70,13 +70,28 @@ enum RTKind : int32_t {
     RT_GRAD = 5,    // adjoint: inner product with a derivative generator
 };
 
-struct RTOp {               // 144 bytes
+// Arithmetic forms of a single-qubit gate inside a register tile.  The
+// Clifford forms are the gate times sqrt(2) (entries 0, +-1, +-i: adds
+// only); the sweep's store rescales by the accumulated power of sqrt(2).
+enum RTForm : int32_t {
+    F_GEN = 0,      // general 2x2 matrix u
+    F_H = 1,        // [[1, 1], [1, -1]]        (sqrt2 H)
+    F_SX = 2,       // [[1, -i], [-i, 1]]       (sqrt2 X^1/2)
+    F_SY = 3,       // [[1, -1], [1, 1]]        (sqrt2 Y^1/2)
+    F_SXDG = 4,     // [[1, i], [i, 1]]
+    F_SYDG = 5,     // [[1, 1], [-1, 1]]
+    F_PHASE = 6,    // diag(1, u[3])
+};
+
+struct RTOp {               // 160 bytes
     int32_t kind;
     int32_t a;              // register slot / lane bit / first term
     int32_t nterms;
     int32_t slot;           // adjoint: gradient slot of this gate, or -1
     double u[8];            // 2x2 complex (re, im) row-major
     double d[8];            // adjoint: derivative generator D (dU = D U)
+    int32_t form;           // RTForm
+    int32_t pad[3];
 };
 
 // A diagonal term: amplitude x is multiplied by `val` (or negated for
@@ -99,7 +114,9 @@ struct RTHeader {           // 64 bytes
     int32_t nterms;
     int32_t op_off;         // byte offset of the RTOp array from the header
     int32_t term_off;       // byte offset of the DiagTerm array
-    int32_t pad[3];
+    int32_t sexp;           // store: amplitudes scaled by 2^sexp ...
+    int32_t shalf;          // ... and by 1/sqrt2 when set
+    int32_t pad;
 };
 
 // LDS-tile ops
@@ -188,6 +205,7 @@ struct SGate {
     int src;         // index of the source gate
     int slot = -1;   // parametrised gate: its gradient slot (list order)
     M2 d{};          // derivative generator of a parametrised gate
+    int form = 0;    // RTForm of the exact gate (F_GEN once altered)
 };
 
 struct PlanRequest {
@@ -206,8 +224,9 @@ sv_status specialise(const sv_circuit *c, int n, std::vector<SGate> *out);
 // Fold single-qubit diagonal gates into neighbouring dense gates on the
 // same qubit (exact algebra, FP64).  With param_safe, parametrised gates
 // are never folded and a diagonal is folded into a parametrised gate only
-// on the side that keeps dU = D U valid.
-void fold_diagonals(std::vector<SGate> *g, int n, bool param_safe = false);
+// on the side that keeps dU = D U valid.  With keep_cheap, gates with an
+// add-only register-tile form are left alone.
+void fold_diagonals(std::vector<SGate> *g, int n, bool param_safe = false, bool keep_cheap = false);
 sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan);
 // Forward and backward sweep sequences of the adjoint gradient, with a
 // checkpoint after every checkpoint_c cycles (0 = none).

@@ -157,6 +157,18 @@ sv_status specialise(const sv_circuit *c, int n, std::vector<SGate> *out) {
         s.q0 = g.q0;
         s.q1 = -1;
         s.src = (int)i;
+        s.form = F_GEN;
+        if (g.param < 0) {
+            switch (g.kind) {
+            case SV_H: s.form = F_H; break;
+            case SV_SX: s.form = F_SX; break;
+            case SV_SY: s.form = F_SY; break;
+            case SV_SXDG: s.form = F_SXDG; break;
+            case SV_SYDG: s.form = F_SYDG; break;
+            default: break;
+            }
+        }
+        if (s.kind == SG_DIAG1 && s.u.m[0].re == 1.0 && s.u.m[0].im == 0.0) s.form = F_PHASE;
         if (g.param >= 0) {
             s.slot = nslot++;
             derivative_generator(g.kind, &s.d);
@@ -166,7 +178,7 @@ sv_status specialise(const sv_circuit *c, int n, std::vector<SGate> *out) {
     return SV_OK;
 }
 
-void fold_diagonals(std::vector<SGate> *gl, int n, bool param_safe) {
+void fold_diagonals(std::vector<SGate> *gl, int n, bool param_safe, bool keep_cheap) {
     std::vector<SGate> &g = *gl;
     std::vector<char> dead(g.size(), 0);
     // per qubit: indices of gates touching it, in order
@@ -195,8 +207,11 @@ void fold_diagonals(std::vector<SGate> *gl, int n, bool param_safe) {
                 if (target >= 0 && param_safe && g[target].slot >= 0) target = -1;
             }
             if (target < 0) continue;   // no dense gate on q: stays a phase
+            // a gate with an add-only form costs less kept apart from the phase
+            if (keep_cheap && g[target].form != F_GEN) continue;
             M2 d = g[i].u;
             g[target].u = before ? m2_mul(g[target].u, d) : m2_mul(d, g[target].u);
+            g[target].form = F_GEN;
             dead[i] = 1;
         }
     }
@@ -325,7 +340,61 @@ static void put_mat(double *dst, const M2 &m) {
     for (int i = 0; i < 4; i++) { dst[2 * i] = m.m[i].re; dst[2 * i + 1] = m.m[i].im; }
 }
 
-static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int vbits, int n) {
+// Reorder a sweep's items so that diagonal items that commute into place
+// form as few runs as possible: alternately take every ready diagonal item
+// and every ready dense item, where an item is ready when no earlier
+// remaining item shares a qubit with it (two diagonal items always commute).
+static std::vector<int> batch_diagonals(const std::vector<SGate> &g, const std::vector<int> &items) {
+    std::vector<int> rem(items), out;
+    auto qubits = [&](int i, int *q) {
+        q[0] = g[i].q0;
+        q[1] = g[i].kind == SG_CZ ? g[i].q1 : -1;
+    };
+    auto diag = [&](int i) { return g[i].kind != SG_DENSE; };
+    bool want_diag = true;
+    int idle = 0;
+    while (!rem.empty()) {
+        std::vector<int> keep;
+        bool took = false;
+        for (size_t a = 0; a < rem.size(); a++) {
+            int i = rem[a];
+            bool ready = diag(i) == want_diag;
+            int qi[2];
+            qubits(i, qi);
+            for (size_t b = 0; ready && b < a; b++) {
+                int j = rem[b];
+                if (j < 0) continue;   // taken in this pass
+                if (diag(i) && diag(j)) continue;
+                int qj[2];
+                qubits(j, qj);
+                for (int x = 0; x < 2; x++)
+                    for (int y = 0; y < 2; y++)
+                        if (qi[x] >= 0 && qi[x] == qj[y]) ready = false;
+            }
+            // items already moved out of rem no longer block anything
+            if (ready) { out.push_back(i); took = true; rem[a] = -1; }
+        }
+        if (want_diag) {
+            // within a diagonal batch: the CZ sign flips first (one run), then
+            // the single-qubit phases
+            size_t first = out.size();
+            while (first > 0 && diag(out[first - 1])) first--;
+            std::stable_partition(out.begin() + first, out.end(),
+                                  [&](int i) { return g[i].kind == SG_CZ; });
+        }
+        for (int i : rem)
+            if (i >= 0) keep.push_back(i);
+        rem.swap(keep);
+        want_diag = !want_diag;
+        idle = took ? 0 : idle + 1;
+        if (idle > 2) break;   // cannot happen: the first remaining item is always ready
+    }
+    for (int i : rem) out.push_back(i);
+    return out;
+}
+
+static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int vbits, int n,
+                               bool cheap = false, int *ncheap = nullptr) {
     RTProgram P;
     RTHeader &h = P.h;
     h.vbits = vbits;
@@ -353,15 +422,22 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
             if ((r & rbits) == rbits) t.regset |= (uint64_t)1 << r;
         return t;
     };
-    for (int idx : sw.items) {
+    int nc = 0;
+    for (int idx : batch_diagonals(g, sw.items)) {
         const SGate &s = g[idx];
-        if (s.kind == SG_DENSE) {
+        const bool in_tile = s.q0 < LANE_BITS || slot[s.q0] >= 0;
+        if (s.kind == SG_DENSE || (s.kind == SG_DIAG1 && in_tile)) {
             RTOp o{};
             if (s.q0 < LANE_BITS) { o.kind = RT_LANE; o.a = s.q0; }
             else { o.kind = RT_REG; o.a = slot[s.q0]; }
             put_mat(o.u, s.u);
             o.slot = s.slot;
             put_mat(o.d, s.d);
+            o.form = s.form;
+            if (s.kind == SG_DENSE && s.form != F_GEN) {
+                if (cheap) nc++;
+                else o.form = F_GEN;
+            }
             ops.push_back(o);
         } else if (s.kind == SG_CZ) {
             DiagTerm t = term_for(bit64(s.q0) | bit64(s.q1));
@@ -408,7 +484,24 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
             }
         }
     }
+    if (ncheap) *ncheap = nc;
     return P;
+}
+
+// Rescaling of the register-tile sweeps of a plan: the add-only forms each
+// multiply the state by sqrt2; sweep i divides by 2^floor(t_i / 2) on store
+// (exact), where t_i is its count plus the half power carried in, and the
+// last sweep also divides by sqrt2 when one is still pending.
+static void assign_scales(Plan *plan, const std::vector<std::pair<size_t, int>> &sweeps) {
+    int carry = 0;
+    for (size_t i = 0; i < sweeps.size(); i++) {
+        RTHeader *h = reinterpret_cast<RTHeader *>(plan->prog.data() + sweeps[i].first);
+        const int t = carry + sweeps[i].second;
+        h->sexp = -(t / 2);
+        carry = t % 2;
+        h->shalf = 0;
+        if (i + 1 == sweeps.size()) { h->shalf = carry; carry = 0; }
+    }
 }
 
 // The adjoint of a register-tile program: ops reversed, matrices and phases
@@ -447,8 +540,11 @@ static void push_regtile(const RTProgram &P, int n, int dtype, OpType type, std:
 }
 
 static void emit_regtile(const std::vector<SGate> &g, const Sweep &sw, int vbits, int n, int dtype,
-                         Plan *plan) {
-    push_regtile(build_regtile(g, sw, vbits, n), n, dtype, OP_REGTILE, &plan->ops, plan);
+                         Plan *plan, std::vector<std::pair<size_t, int>> *scales) {
+    int nc = 0;
+    RTProgram P = build_regtile(g, sw, vbits, n, true, &nc);
+    push_regtile(P, n, dtype, OP_REGTILE, &plan->ops, plan);
+    scales->push_back({plan->ops.back().prog_off, nc});
 }
 
 // ---------------------------------------------------------------------------
@@ -739,7 +835,7 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
         r2.mode = mode;
         plan_per_gate(c, g, r2, plan);
     } else if (mode == SV_MODE_REGTILE) {
-        fold_diagonals(&g, rq.n);
+        fold_diagonals(&g, rq.n, false, true);
         int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 5 : 4);
         vb = std::max(1, std::min(vb, rq.dtype == SV_C64 ? 6 : 5));
         vb = std::min(vb, rq.n - LANE_BITS);
@@ -750,7 +846,9 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
                 if (g[i].kind == SG_CZ) q.push_back(g[i].q1);
                 return q;
             });
-        for (const Sweep &sw : sweeps) emit_regtile(g, sw, vb, rq.n, rq.dtype, plan);
+        std::vector<std::pair<size_t, int>> scales;
+        for (const Sweep &sw : sweeps) emit_regtile(g, sw, vb, rq.n, rq.dtype, plan, &scales);
+        assign_scales(plan, scales);
     } else {
         fold_diagonals(&g, rq.n);
         int kmax = rq.k_max > 0 ? std::min(rq.k_max, 5) : 4;

@@ -82,8 +82,20 @@ __global__ __launch_bounds__(RB) void k_stats(const cpx<T> *__restrict__ psi, ui
     for (int i = 0; i < NSTAT; i++) acc[i] = 0.0;
     unsigned long long zeros = 0;
     const uint64_t start = (uint64_t)blockIdx.x * chunk;
-    for (uint64_t j = start + threadIdx.x; j < start + chunk; j += RB) {
-        const double p = prob_of(psi[j]);
+    // UNR loads in flight per thread before any use (chunk is a multiple of
+    // RB * UNR whenever the state has at least 2^12 amplitudes)
+    constexpr int UNR = 8;
+    const uint64_t step = (chunk % (RB * UNR) == 0) ? RB * UNR : RB;
+    const int unr = (step == RB * UNR) ? UNR : 1;
+    for (uint64_t j0 = start + threadIdx.x; j0 < start + chunk; j0 += step) {
+      cpx<T> buf[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; u++)
+          if (u < unr) buf[u] = psi[j0 + (uint64_t)u * RB];
+#pragma unroll
+      for (int u = 0; u < UNR; u++) {
+        if (u >= unr) break;
+        const double p = prob_of(buf[u]);
         acc[0] += p;
         if (FULL) {
             if (p > 0.0) {
@@ -101,6 +113,7 @@ __global__ __launch_bounds__(RB) void k_stats(const cpx<T> *__restrict__ psi, ui
                 uk *= u;
             }
         }
+      }
     }
     block_sum<double, NSTAT>(acc, red);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -311,9 +324,17 @@ __global__ __launch_bounds__(RB) void k_scatter(int64_t k, const uint32_t *__res
     bucket[bstart[b] + pos] = (uint32_t)i;
 }
 
-// One workgroup per bucket holding samples: prefix sums of the weights by
-// thread stretch, then each sample walks its stretch to the first entry
-// whose running sum exceeds the target (x = min{j : C_j > t}).
+// One workgroup per bucket holding samples.  The bucket (2^bs weights) is
+// read in rounds of RB * RS entries, coalesced into LDS; within a round
+// thread t owns the contiguous stretch [RS t, RS t + RS).  Stretch sums are
+// scanned in (round, thread) order, so stretch k covers entries
+// [RS k, RS k + RS) of the bucket.  Each sample then binary-searches the
+// stretch prefixes and walks one stretch to the first entry whose running
+// sum exceeds its target (x = min{j : C_j > t}).
+constexpr int RS = 16;                 // entries per stretch
+constexpr int RROUND = RB * RS;        // entries per round (4096)
+constexpr int MAXSTRETCH = (1 << 16) / RS;
+
 template <typename S>
 __global__ __launch_bounds__(RB) void k_resolve(const S *__restrict__ src, int bs,
                                                 const unsigned long long *__restrict__ counts,
@@ -324,32 +345,58 @@ __global__ __launch_bounds__(RB) void k_resolve(const S *__restrict__ src, int b
     const uint64_t b = blockIdx.x;
     const unsigned long long cnt = counts[b];
     if (cnt == 0) return;
-    __shared__ unsigned long long pre[RB + 1];
+    __shared__ unsigned long long stage[RROUND];
+    __shared__ unsigned long long pre[MAXSTRETCH + 1];
     const uint64_t len = 1ull << bs;
-    const uint64_t per = (len + RB - 1) / RB;
+    const int nstretch = (int)((len + RS - 1) / RS);
     const uint64_t start = b << bs;
-    const uint64_t lb = threadIdx.x * per;
-    const uint64_t le = lb + per < len ? lb + per : len;
-    unsigned long long s = 0;
-    for (uint64_t j = lb; j < le; j++) s += weight_of(prob_of(src[start + j]));
-    pre[threadIdx.x + 1] = s;
+    for (uint64_t r0 = 0; r0 < len; r0 += RROUND) {
+#pragma unroll
+        for (int i = 0; i < RS; i++) {
+            const uint64_t j = r0 + threadIdx.x + (uint64_t)i * RB;
+            stage[threadIdx.x + i * RB] = j < len ? weight_of(prob_of(src[start + j])) : 0ull;
+        }
+        __syncthreads();
+        const int k = (int)(r0 / RS) + threadIdx.x;
+        if (k < nstretch) {
+            unsigned long long s = 0;
+#pragma unroll
+            for (int i = 0; i < RS; i++) s += stage[threadIdx.x * RS + i];
+            pre[k + 1] = s;
+        }
+        __syncthreads();
+    }
+    // inclusive scan of stretch sums into pre[1..nstretch], pre[0] = 0
     if (threadIdx.x == 0) pre[0] = 0;
     __syncthreads();
-    if (threadIdx.x == 0)
-        for (int i = 1; i <= RB; i++) pre[i] += pre[i - 1];
+    {
+        const int per = (nstretch + RB - 1) / RB;
+        const int lo = threadIdx.x * per;
+        const int hi = lo + per < nstretch ? lo + per : nstretch;
+        unsigned long long run = 0;
+        for (int k = lo; k < hi; k++) { run += pre[k + 1]; pre[k + 1] = run; }
+        __shared__ unsigned long long tsum[RB];
+        tsum[threadIdx.x] = run;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int i = 1; i < RB; i++) tsum[i] += tsum[i - 1];
+        __syncthreads();
+        const unsigned long long add = threadIdx.x ? tsum[threadIdx.x - 1] : 0ull;
+        for (int k = lo; k < hi; k++) pre[k + 1] += add;
+    }
     __syncthreads();
     const unsigned long long b0 = bstart[b];
     for (unsigned long long q = threadIdx.x; q < cnt; q += RB) {
         const uint32_t smp = bucket[b0 + q];
         const unsigned long long t = tloc[smp];
-        int lo = 0, hi = RB;   // last stretch with pre[c] <= t
+        int lo = 0, hi = nstretch;   // last stretch with pre[k] <= t
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (pre[mid] <= t) lo = mid; else hi = mid;
         }
         unsigned long long run = pre[lo];
-        const uint64_t jb = (uint64_t)lo * per;
-        const uint64_t je = jb + per < len ? jb + per : len;
+        const uint64_t jb = (uint64_t)lo * RS;
+        const uint64_t je = jb + RS < len ? jb + RS : len;
         uint64_t ans = je - 1;
         for (uint64_t j = jb; j < je; j++) {
             run += weight_of(prob_of(src[start + j]));

@@ -145,9 +145,9 @@ __global__ __launch_bounds__(BLOCK) void k_regtile(cplx<T> *__restrict__ psi,
         const int kind = ops[o].kind;
         const int arg = ops[o].a;
         if (kind == RT_REG) {
-            reg_gate_dispatch<T, NR>(a, load_mat<T>(ops[o].u), arg);
+            reg_gate_dispatch<T, NR>(a, load_mat<T>(ops[o].u), arg, ops[o].form);
         } else if (kind == RT_LANE) {
-            lane_gate_dispatch<T, NR>(a, load_mat<T>(ops[o].u), arg, lane);
+            lane_gate_dispatch<T, NR>(a, load_mat<T>(ops[o].u), arg, lane, ops[o].form);
         } else if (kind == RT_SIGNS) {
             uint64_t par = 0;
             const int nt = ops[o].nterms;
@@ -174,6 +174,23 @@ __global__ __launch_bounds__(BLOCK) void k_regtile(cplx<T> *__restrict__ psi,
                 for (int r = 0; r < NR; r++)
                     if ((rs >> r) & 1) a[r] = cmul(v, a[r]);
             }
+        }
+    }
+    // the Clifford forms leave a power of sqrt2: 2^sexp exactly, then 1/sqrt2
+    const int sexp = h->sexp;
+    if (sexp != 0) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            a[r].re = ldexp(a[r].re, sexp);
+            a[r].im = ldexp(a[r].im, sexp);
+        }
+    }
+    if (h->shalf) {
+        const T rs = (T)0.70710678118654752440;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            a[r].re *= rs;
+            a[r].im *= rs;
         }
     }
     cplx<T> *dst = psi + base + lane;

@@ -94,6 +94,8 @@ EXPORTS = {
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sv_host_emulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_void_p]),
+    "sv_host_plan_describe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_int, ctypes.c_char_p, ctypes.c_int64]),
 }
 
 _lib = None
@@ -302,3 +304,12 @@ def host_emulate(circ, psi: np.ndarray, dtype="c64", mode="auto", k_max=0, tile=
     check(lib().sv_host_emulate(a.ref, C64 if dtype == "c64" else C128, ctypes.byref(o),
                                 1 if from_zero else 0, _ptr(psi)))
     return psi
+
+
+def host_plan_describe(circ, dtype="c64", mode="auto", k_max=0, tile=0, from_zero=True) -> str:
+    a = CircuitArgs(circ)
+    o = make_opts(mode, k_max, tile)
+    buf = ctypes.create_string_buffer(1 << 20)
+    check(lib().sv_host_plan_describe(a.ref, C64 if dtype == "c64" else C128, ctypes.byref(o),
+                                      1 if from_zero else 0, buf, len(buf)))
+    return buf.value.decode()
