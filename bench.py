@@ -176,19 +176,32 @@ def mode_timings(sv, C, circ, torch):
     for dtype in ("c64", "c128"):
         st = sv.State(circ.n, dtype)
         args = sv.CircuitArgs(circ)
-        modes = [("plain", 0, 0), ("spec", 0, 0), ("fused", 2, 0), ("fused", 3, 0), ("fused", 4, 0),
-                 ("fused", 5, 0), ("tiled", 4, 13 if dtype == "c64" else 12),
-                 ("regtile", 0, 5), ("regtile", 0, 6 if dtype == "c64" else 5)]
-        for mode, k, t in modes:
-            st.apply(circ, mode, k, t, args=args, from_zero=True)   # plan + warm
+        modes = [("plain", 0, 0, False), ("spec", 0, 0, False), ("fused", 2, 0, False),
+                 ("fused", 3, 0, False), ("fused", 4, 0, False), ("fused", 5, 0, False),
+                 ("tiled", 3, 12 if dtype == "c64" else 11, False),
+                 ("tiled", 4, 13 if dtype == "c64" else 12, False)]
+        if dtype == "c64":
+            modes += [("fused", 4, 0, True), ("fused", 5, 0, True), ("regtile", 0, 4, False),
+                      ("regtile", 0, 5, False), ("regtile", 0, 6, False)]
+        else:
+            modes += [("regtile", 0, 3, False), ("regtile", 0, 4, False)]
+        modes += [("auto", 0, 0, False)]
+        for mode, k, t, nomf in modes:
+            st.apply(circ, mode, k, t, args=args, from_zero=True, no_mfma=nomf)   # plan + warm / tune
+            if mode == "auto":
+                for _ in range(8):
+                    st.apply(circ, mode, k, t, args=args, from_zero=True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            st.apply(circ, mode, k, t, args=args, from_zero=True)
+            st.apply(circ, mode, k, t, args=args, from_zero=True, no_mfma=nomf)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            sw, by = st.plan_info(circ, mode, k, t)
-            key = "%s_%s%s" % (dtype, mode, ("_k%d" % k if k else "") + ("_t%d" % t if t else ""))
+            sw, by = st.plan_info(circ, mode, k, t, no_mfma=nomf)
+            key = "%s_%s%s%s" % (dtype, mode, ("_k%d" % k if k else "") + ("_t%d" % t if t else ""),
+                                 "_valu" if nomf else "")
             res[key] = {"s": round(dt, 4), "sweeps": sw, "GBps": round(by / dt / 1e9, 1)}
+            if mode == "auto":
+                res[key]["choice"] = st.autotune(circ, from_zero=True)[:3]
             log("%s: %.3f s, %d sweeps" % (key, dt, sw))
         st.close()
         del st

@@ -100,7 +100,9 @@ enum {
 
 /* sv_opts.flags bits */
 enum {
-    SV_FLAG_FROM_ZERO = 1   /* ignore the current contents: simulate U|0...0> */
+    SV_FLAG_FROM_ZERO = 1,  /* ignore the current contents: simulate U|0...0> */
+    SV_FLAG_NO_MFMA = 2     /* fused blocks with k >= 4 on the VALU instead of
+                               the matrix cores (for comparison)             */
 };
 
 typedef struct {
@@ -154,9 +156,21 @@ sv_status sv_data(sv_state *st, void **dev_ptr);
 sv_status sv_apply_circuit(sv_state *st, const sv_circuit *c, const sv_opts *opts);
 
 /* Number of sweeps over the state the plan for (c, opts) performs, and the
- * algorithmic bytes it moves (reads + writes of the state). */
+ * algorithmic bytes it moves (reads + writes of the state).  For
+ * SV_MODE_AUTO this tunes first if needed (see sv_autotune). */
 sv_status sv_plan_info(sv_state *st, const sv_circuit *c, const sv_opts *opts,
                        int64_t *sweeps, double *bytes);
+
+/* Autotuner behind SV_MODE_AUTO: times candidate plans for c on this device
+ * -- register tiles with 4, 5 or 6 register qubits (complex64) and 3 or 4
+ * (complex128), fused blocks with k = 2 and 3, LDS tiles -- and keeps the
+ * fastest for the circuit (cached per process).  The timing runs on a
+ * scratch state of the same size when the device has room for one (the
+ * handle's contents are untouched); otherwise successive sv_apply_circuit
+ * calls on the handle each run the next untried candidate (every call is
+ * still exact).  chosen (may be NULL) gets the selected options;
+ * *complete = 1 once the choice is final. */
+sv_status sv_autotune(sv_state *st, const sv_circuit *c, int from_zero, sv_opts *chosen, int *complete);
 
 /* Sweep kinds reported by sv_apply_circuit_timed. */
 enum {

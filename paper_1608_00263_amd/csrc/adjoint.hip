@@ -118,8 +118,8 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
     cplx<T> phi[NR], mu[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-        phi[r] = phi_g[base + reg_offset<VB>(bq, r) + lane];
-        mu[r] = mu_g[base + reg_offset<VB>(bq, r) + lane];
+        phi[r] = uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r)))[lane];
+        mu[r] = uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r)))[lane];
     }
     const RTOp *ops = reinterpret_cast<const RTOp *>(prog + h->op_off);
     const DiagTerm *terms = reinterpret_cast<const DiagTerm *>(prog + h->term_off);
@@ -190,8 +190,8 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
     }
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-        phi_g[base + reg_offset<VB>(bq, r) + lane] = phi[r];
-        mu_g[base + reg_offset<VB>(bq, r) + lane] = mu[r];
+        uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r)))[lane] = phi[r];
+        uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r)))[lane] = mu[r];
     }
 }
 

@@ -75,11 +75,128 @@ static PlanRequest make_request(sv_state *st, const sv_opts *o) {
     rq.tile = o ? o->tile_qubits : 0;
     rq.force_zero = o && (o->flags & SV_FLAG_FROM_ZERO);
     rq.from_zero = st->known_zero || rq.force_zero;
+    rq.no_mfma = o && (o->flags & SV_FLAG_NO_MFMA);
     return rq;
 }
 
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+static std::map<std::string, sv_opts> g_tuned;   // process-wide choices
+
+static std::vector<sv_opts> tune_candidates(const sv_state *st) {
+    std::vector<sv_opts> c;
+    auto add = [&](int mode, int k, int t) { c.push_back(sv_opts{mode, k, t, 0}); };
+    if (st->n >= 10) {
+        if (st->dt == SV_C64) { add(SV_MODE_REGTILE, 0, 4); add(SV_MODE_REGTILE, 0, 5); add(SV_MODE_REGTILE, 0, 6); }
+        else { add(SV_MODE_REGTILE, 0, 3); add(SV_MODE_REGTILE, 0, 4); }
+        add(SV_MODE_FUSED, 2, 0);
+        add(SV_MODE_FUSED, 3, 0);
+        add(SV_MODE_TILED, 3, st->dt == SV_C64 ? 12 : 11);
+    } else {
+        add(SV_MODE_SPEC, 0, 0);
+    }
+    return c;
+}
+
+static std::string tune_key(const sv_state *st, const sv_circuit *c, bool from_zero) {
+    PlanRequest rq{};
+    rq.n = st->n;
+    rq.dtype = st->dt;
+    rq.mode = SV_MODE_AUTO;
+    rq.from_zero = from_zero;
+    return plan_key(c, rq);
+}
+
+static sv_status time_plan(sv_state *st, const Plan &plan, void *psi, float *ms) {
+    hipEvent_t a, b;
+    SV_HIP(hipEventCreate(&a));
+    SV_HIP(hipEventCreate(&b));
+    sv_status rc = SV_OK;
+    (void)hipEventRecord(a, st->stream);
+    for (const Op &op : plan.ops) {
+        rc = launch_op(st, plan, op, psi);
+        if (rc != SV_OK) break;
+    }
+    (void)hipEventRecord(b, st->stream);
+    hipError_t e = hipEventSynchronize(b);
+    if (rc == SV_OK && e != hipSuccess) rc = hip_fail(e, "hipEventSynchronize");
+    if (rc == SV_OK) (void)hipEventElapsedTime(ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return rc;
+}
+
+// Resolve SV_MODE_AUTO to concrete options for (st, c).  May run the
+// scratch-state tuning; sets *explore when this call should instead time a
+// candidate on the real state.
+static sv_status resolve_auto(sv_state *st, const sv_circuit *c, bool from_zero, sv_opts *out, int *explore) {
+    *explore = -1;
+    const std::string key = tune_key(st, c, from_zero);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) { *out = it->second; return SV_OK; }
+    std::vector<sv_opts> cand = tune_candidates(st);
+    if (cand.size() == 1) { g_tuned[key] = cand[0]; *out = cand[0]; return SV_OK; }
+    const size_t bytes = (size_t)state_bytes(st->n, st->dt);
+    size_t freeb = 0, total = 0;
+    SV_HIP(hipMemGetInfo(&freeb, &total));
+    if (freeb > bytes + bytes / 4 + ((size_t)1 << 30)) {
+        void *scratch = nullptr;
+        SV_HIP(hipMalloc(&scratch, bytes));
+        SV_HIP(hipMemsetAsync(scratch, 0, bytes, st->stream));
+        int best = -1;
+        float best_ms = 0;
+        sv_status rc = SV_OK;
+        for (size_t i = 0; i < cand.size() && rc == SV_OK; i++) {
+            PlanRequest rq = make_request(st, &cand[i]);
+            rq.from_zero = from_zero;
+            std::shared_ptr<Plan> plan;
+            rc = get_plan(st, c, rq, &plan);
+            float ms = 0;
+            if (rc == SV_OK) rc = time_plan(st, *plan, scratch, &ms);           // warm
+            if (rc == SV_OK) rc = time_plan(st, *plan, scratch, &ms);
+            if (rc == SV_OK && (best < 0 || ms < best_ms)) { best = (int)i; best_ms = ms; }
+        }
+        (void)hipStreamSynchronize(st->stream);
+        (void)hipFree(scratch);
+        if (rc != SV_OK) return rc;
+        g_tuned[key] = cand[best];
+        *out = cand[best];
+        return SV_OK;
+    }
+    // no room for a scratch state: explore on the real calls
+    Tune &t = st->tunes[key];
+    if (t.cand.empty()) { t.cand = cand; t.ms.assign(cand.size(), 0.0); }
+    if (t.next < t.cand.size()) {
+        *explore = (int)t.next;
+        *out = t.cand[t.next];
+        return SV_OK;
+    }
+    int best = 0;
+    for (size_t i = 1; i < t.ms.size(); i++)
+        if (t.ms[i] < t.ms[best]) best = (int)i;
+    g_tuned[key] = t.cand[best];
+    *out = t.cand[best];
+    return SV_OK;
+}
+
+// Options actually used for a call (AUTO resolved).
+static sv_status effective_opts(sv_state *st, const sv_circuit *c, const sv_opts *o, sv_opts *eff,
+                                int *explore) {
+    *explore = -1;
+    sv_opts d{SV_MODE_AUTO, 0, 0, 0};
+    if (o) d = *o;
+    if (d.mode != SV_MODE_AUTO) { *eff = d; return SV_OK; }
+    const bool from_zero = st->known_zero || (d.flags & SV_FLAG_FROM_ZERO);
+    sv_opts r;
+    SV_TRY(resolve_auto(st, c, from_zero, &r, explore));
+    r.flags = d.flags;
+    *eff = r;
+    return SV_OK;
+}
+
 sv_status get_plan(sv_state *st, const sv_circuit *c, PlanRequest rq, std::shared_ptr<Plan> *out) {
-    if (rq.mode == SV_MODE_AUTO) rq.mode = SV_MODE_REGTILE;
+    if (rq.mode == SV_MODE_AUTO) rq.mode = SV_MODE_REGTILE;   // only without a handle-level choice
     if (rq.mode < SV_MODE_PLAIN || rq.mode > SV_MODE_REGTILE) return fail(SV_EINVAL, "unknown mode");
     if (rq.k_max < 0 || rq.k_max > 5) return fail(SV_EINVAL, "k_max must be 0..5");
     std::string key = plan_key(c, rq);
@@ -202,9 +319,31 @@ sv_status sv_data(sv_state *st, void **dev_ptr) {
 sv_status sv_apply_circuit(sv_state *st, const sv_circuit *c, const sv_opts *opts) {
     SV_TRY(check_state(st));
     SV_TRY(check_circuit(st, c));
+    sv_opts eff;
+    int explore = -1;
+    SV_TRY(effective_opts(st, c, opts, &eff, &explore));
     std::shared_ptr<Plan> plan;
-    SV_TRY(get_plan(st, c, make_request(st, opts), &plan));
-    return run_plan(st, *plan);
+    const bool from_zero = st->known_zero || (eff.flags & SV_FLAG_FROM_ZERO);
+    SV_TRY(get_plan(st, c, make_request(st, &eff), &plan));
+    if (explore < 0) return run_plan(st, *plan);
+    float ms = 0;
+    SV_TRY(time_plan(st, *plan, st->data, &ms));
+    st->known_zero = false;
+    Tune &t = st->tunes[tune_key(st, c, from_zero)];
+    t.ms[explore] = ms;
+    t.next++;
+    return SV_OK;
+}
+
+sv_status sv_autotune(sv_state *st, const sv_circuit *c, int from_zero, sv_opts *chosen, int *complete) {
+    SV_TRY(check_state(st));
+    SV_TRY(check_circuit(st, c));
+    sv_opts r;
+    int explore = -1;
+    SV_TRY(resolve_auto(st, c, from_zero != 0, &r, &explore));
+    if (chosen) *chosen = r;
+    if (complete) *complete = explore < 0;
+    return SV_OK;
 }
 
 static int32_t sweep_kind(const Op &op) {
@@ -226,8 +365,11 @@ sv_status sv_apply_circuit_timed(sv_state *st, const sv_circuit *c, const sv_opt
                                  float *op_ms, int32_t *op_kind, double *op_bytes, int64_t *nops) {
     SV_TRY(check_state(st));
     SV_TRY(check_circuit(st, c));
+    sv_opts eff;
+    int explore = -1;
+    SV_TRY(effective_opts(st, c, opts, &eff, &explore));
     std::shared_ptr<Plan> plan;
-    SV_TRY(get_plan(st, c, make_request(st, opts), &plan));
+    SV_TRY(get_plan(st, c, make_request(st, &eff), &plan));
     const size_t m = plan->ops.size();
     std::vector<hipEvent_t> ev(m + 1);
     for (auto &e : ev) SV_HIP(hipEventCreate(&e));
@@ -264,8 +406,11 @@ sv_status sv_plan_info(sv_state *st, const sv_circuit *c, const sv_opts *opts, i
                        double *bytes) {
     SV_TRY(check_state(st));
     SV_TRY(check_circuit(st, c));
+    sv_opts eff;
+    int explore = -1;
+    SV_TRY(effective_opts(st, c, opts, &eff, &explore));
     std::shared_ptr<Plan> plan;
-    SV_TRY(get_plan(st, c, make_request(st, opts), &plan));
+    SV_TRY(get_plan(st, c, make_request(st, &eff), &plan));
     if (sweeps) *sweeps = plan->sweeps;
     if (bytes) *bytes = plan->bytes;
     return SV_OK;

@@ -212,6 +212,17 @@ __device__ __forceinline__ void lane_gate_dispatch(cplx<T> (&a)[NR], const Mat2<
     }
 }
 
+// A wave-uniform pointer held in scalar registers, so that a wave-wide
+// access ptr[lane] uses the scalar-base + 32-bit lane-offset address form
+// (one address register per lane for all rows of a tile).
+template <typename P>
+__device__ __forceinline__ P *uniform_ptr(P *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P *)(((uint64_t)hi << 32) | lo);
+}
+
 // Offset of register r in a register tile: sum of 2^rq[i] over the set
 // bits i of r (r is a compile-time constant after unrolling).
 template <int VB>

@@ -36,7 +36,15 @@ static void emulate_regtile(const Plan &plan, const Op &op, int n, cx *psi) {
         uint64_t base = tile << LANE_BITS;
         for (int i = 0; i < vb; i++) base = ins0(base, h->rq[i]);
         for (int l = 0; l < 64; l++)
-            for (int r = 0; r < nr; r++) a[l * nr + r] = psi[base + roff[r] + l];
+            for (int r = 0; r < nr; r++) {
+                if (h->gen_n > 0) {
+                    double v = std::ldexp(1.0, -(h->gen_n / 2));
+                    if (h->gen_n & 1) v /= std::sqrt(2.0);
+                    a[l * nr + r] = f32 ? (double)(float)v : v;
+                } else {
+                    a[l * nr + r] = psi[base + roff[r] + l];
+                }
+            }
         for (int o = 0; o < h->nops; o++) {
             const RTOp &p = ops[o];
             cx u[4];
@@ -125,7 +133,18 @@ static void emulate_ldstile(const Plan &plan, const Op &op, int n, cx *psi) {
             if (p.kind == LT_BLOCK) {
                 const int k = p.k, d = 1 << k;
                 std::vector<cx> U(d * d);
-                for (int i = 0; i < d * d; i++) {
+                if (p.mfma) {
+                    // rebuild U from the lane-ordered real embedding
+                    const float *f = (const float *)(prog + p.mat_off);
+                    for (int a = 0; a < d; a++)
+                        for (int b = 0; b < d; b++) {
+                            const int row = 2 * a, mb = row / 32, l = row % 32;       // ra = 0
+                            const double ur = f[((size_t)mb * d + b) * 64 + l];        // rb = 0: Ur
+                            const double mi = f[((size_t)mb * d + b) * 64 + 32 + l];   // rb = 1: -Ui
+                            U[a * d + b] = cx(ur, -mi);
+                        }
+                }
+                for (int i = 0; i < d * d && !p.mfma; i++) {
                     if (f32) {
                         const float *f = (const float *)(prog + p.mat_off);
                         U[i] = cx(f[2 * i], f[2 * i + 1]);

@@ -116,7 +116,8 @@ struct RTHeader {           // 64 bytes
     int32_t term_off;       // byte offset of the DiagTerm array
     int32_t sexp;           // store: amplitudes scaled by 2^sexp ...
     int32_t shalf;          // ... and by 1/sqrt2 when set
-    int32_t pad;
+    int32_t gen_n;          // > 0: do not load; start from the uniform state
+                            // 2^{-gen_n/2} of gen_n qubits (Hadamard layer)
 };
 
 // LDS-tile ops
@@ -133,7 +134,8 @@ struct LTOp {               // 64 bytes
     int32_t mat_off;        // byte offset of the matrix from the header
     int32_t nterms;
     int32_t term0;
-    int32_t pad[6];
+    int32_t mfma;           // LT_BLOCK with k >= 4: run on the matrix cores
+    int32_t pad[5];
 };
 
 struct LTTerm {             // 32 bytes
@@ -217,6 +219,7 @@ struct PlanRequest {
     bool from_zero;      // state is |0..0>: a leading Hadamard layer may be
                          // replaced by the uniform initialisation
     bool force_zero;     // the plan must itself start from |0..0>
+    bool no_mfma;        // k >= 4 blocks on the VALU
 };
 
 // Validate the circuit and produce the specialised gate list in order.
@@ -246,6 +249,16 @@ struct Workspace {
 
 }  // namespace svi
 
+namespace svi {
+// autotuner record for one circuit
+struct Tune {
+    std::vector<sv_opts> cand;
+    std::vector<double> ms;
+    size_t next = 0;
+    int best = -1;
+};
+}  // namespace svi
+
 struct sv_state {
     int n = 0;
     sv_dtype dt = SV_C64;
@@ -257,6 +270,7 @@ struct sv_state {
     svi::Workspace ws;           // reductions, sampler
     svi::Workspace ws2;          // adjoint second state / checkpoints
     std::map<std::string, std::shared_ptr<svi::Plan>> plans;
+    std::map<std::string, svi::Tune> tunes;   // explore-on-use records
 };
 
 namespace svi {

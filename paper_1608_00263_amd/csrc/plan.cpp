@@ -284,7 +284,10 @@ struct Sweep {
 // commute).
 static std::vector<Sweep> group_sweeps(int nitems, int n, int cap,
                                        const std::function<bool(int)> &diag,
-                                       const std::function<std::vector<int>(int)> &qubits) {
+                                       const std::function<std::vector<int>(int)> &qubits,
+                                       const std::function<double(int, const std::vector<char> &)> &cost =
+                                           nullptr,
+                                       double budget = 0) {
     std::vector<Sweep> out;
     std::vector<char> done(nitems, 0);
     int left = nitems;
@@ -296,6 +299,7 @@ static std::vector<Sweep> group_sweeps(int nitems, int n, int cap,
         std::fill(in_tile.begin(), in_tile.end(), 0);
         for (int q = 0; q < std::min(n, LANE_BITS); q++) in_tile[q] = 1;
         int ngather = 0;
+        double spent = 0;
         for (int i = 0; i < nitems; i++) {
             if (done[i]) continue;
             std::vector<int> qs = qubits(i);
@@ -303,12 +307,22 @@ static std::vector<Sweep> group_sweeps(int nitems, int n, int cap,
             bool ok = true;
             for (int q : qs)
                 if (block_all[q] || (!d && block_dense[q])) ok = false;
+            int need = 0;
             if (ok && !d) {
-                int need = 0;
                 for (int q : qs)
                     if (!in_tile[q]) need++;
                 if (ngather + need > cap) ok = false;
-                else
+            }
+            // arithmetic budget of a sweep (the first item always fits)
+            if (ok && cost && !sw.items.empty()) {
+                std::vector<char> t2(in_tile);
+                for (int q : qs) t2[q] = 1;
+                double c = cost(i, d ? in_tile : t2);
+                if (spent + c > budget) ok = false;
+            }
+            if (ok) {
+                if (cost) spent += cost(i, in_tile);
+                if (!d)
                     for (int q : qs)
                         if (!in_tile[q]) { in_tile[q] = 1; sw.tile.push_back(q); ngather++; }
             }
@@ -648,7 +662,8 @@ struct LTItem {          // an op of an LDS tile program before encoding
 };
 
 static void emit_ldstile(const std::vector<SGate> &g, const std::vector<const Block *> &items,
-                         const std::vector<int> &tile, int mbits, int n, int dtype, Plan *plan) {
+                         const std::vector<int> &tile, int mbits, int n, int dtype, Plan *plan,
+                         bool no_mfma = false) {
     LTHeader h{};
     h.mbits = mbits;
     std::vector<int> hq(tile.begin(), tile.end());
@@ -705,16 +720,31 @@ static void emit_ldstile(const std::vector<SGate> &g, const std::vector<const Bl
         o.kind = LT_BLOCK;
         o.k = (int)B->qubits.size();
         for (int j = 0; j < o.k; j++) o.pos[j] = local[B->qubits[j]];
-        if (o.k >= 4 && dtype == SV_C64) mfma = true;
+        if (o.k >= 4 && dtype == SV_C64 && !no_mfma) { mfma = true; o.mfma = 1; }
         mats.push_back({ops.size(), block_matrix(g, *B)});
         ops.push_back(o);
     }
     h.nops = (int)ops.size();
     size_t hoff = push_struct(&plan->prog, h);
-    // matrices in the state precision
+    // matrices in the state precision; matrix-core blocks get their real
+    // embedding E[2a + ra][2b + rb] (Ur on ra == rb, -Ui for (0,1), Ui for
+    // (1,0)) laid out as the A operands of v_mfma_f32_32x32x2f32: for M block
+    // mb and step b, lane l holds E[l % 32 + 32 mb][2 b + l / 32]
     for (auto &pm : mats) {
         size_t off;
-        if (dtype == SV_C64) {
+        const LTOp &bop = ops[pm.first];
+        if (bop.mfma) {
+            const int d = 1 << bop.k, nmb = d / 16;
+            std::vector<float> f((size_t)nmb * d * 64);
+            for (int mb = 0; mb < nmb; mb++)
+                for (int b = 0; b < d; b++)
+                    for (int l = 0; l < 64; l++) {
+                        const int row = l % 32 + 32 * mb, a = row / 2, ra = row % 2, rb = l / 32;
+                        const cd u = pm.second[(size_t)a * d + b];
+                        f[((size_t)mb * d + b) * 64 + l] = (float)(ra == rb ? u.re : (ra == 0 ? -u.im : u.im));
+                    }
+            off = push_bytes(&plan->prog, f.data(), f.size() * sizeof(float));
+        } else if (dtype == SV_C64) {
             std::vector<float> f(pm.second.size() * 2);
             for (size_t i = 0; i < pm.second.size(); i++) {
                 f[2 * i] = (float)pm.second[i].re;
@@ -736,6 +766,9 @@ static void emit_ldstile(const std::vector<SGate> &g, const std::vector<const Bl
     op.vbits = mbits;
     op.prog_off = hoff;
     op.mfma = mfma;
+    op.q1 = 0;   // widest block (selects the kernel variant)
+    for (const LTOp &o : ops)
+        if (o.kind == LT_BLOCK) op.q1 = std::max(op.q1, o.k);
     op.bytes = 2 * state_bytes(n, dtype);
     plan->ops.push_back(op);
 }
@@ -786,6 +819,34 @@ static void plan_per_gate(const sv_circuit *c, const std::vector<SGate> &g, cons
         plan->ops.push_back(op);
     }
     (void)c;
+}
+
+// Register-tile grouping with an arithmetic budget per sweep.  Costs are
+// vector instructions per amplitude register of a lane (the sweep's memory
+// time allows about 110 of them at complex64 and twice that at complex128):
+// add-only forms 2 on a register qubit and 5 on a lane qubit (cross-lane
+// moves), general 2x2 gates 8 and 11, phases 2 (register) or 4, and 1 per CZ
+// sign flip.
+static std::vector<Sweep> regtile_sweeps(const std::vector<SGate> &g, int n, int vb, int dtype,
+                                         double budget = -1) {
+    if (budget < 0) budget = dtype == SV_C64 ? 110.0 : 220.0;
+    auto cost = [&](int i, const std::vector<char> &in_tile) -> double {
+        const SGate &s = g[i];
+        if (s.kind == SG_CZ) return 1.0;
+        const bool lane = s.q0 < LANE_BITS;
+        const bool reg = !lane && in_tile[s.q0];
+        if (s.kind == SG_DIAG1) return reg ? 2.0 : 4.0;
+        const bool cheap = s.form != F_GEN;
+        return lane ? (cheap ? 5.0 : 11.0) : (cheap ? 2.0 : 8.0);
+    };
+    return group_sweeps(
+        (int)g.size(), n, vb, [&](int i) { return g[i].kind != SG_DENSE; },
+        [&](int i) {
+            std::vector<int> q = {g[i].q0};
+            if (g[i].kind == SG_CZ) q.push_back(g[i].q1);
+            return q;
+        },
+        cost, budget);
 }
 
 std::string plan_key(const sv_circuit *c, const PlanRequest &rq) {
@@ -839,16 +900,19 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
         int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 5 : 4);
         vb = std::max(1, std::min(vb, rq.dtype == SV_C64 ? 6 : 5));
         vb = std::min(vb, rq.n - LANE_BITS);
-        auto sweeps = group_sweeps(
-            (int)g.size(), rq.n, vb, [&](int i) { return g[i].kind != SG_DENSE; },
-            [&](int i) {
-                std::vector<int> q = {g[i].q0};
-                if (g[i].kind == SG_CZ) q.push_back(g[i].q1);
-                return q;
-            });
+        auto sweeps = regtile_sweeps(g, rq.n, vb, rq.dtype);
         std::vector<std::pair<size_t, int>> scales;
         for (const Sweep &sw : sweeps) emit_regtile(g, sw, vb, rq.n, rq.dtype, plan, &scales);
         assign_scales(plan, scales);
+        // the uniform initialisation is generated inside the first sweep's
+        // registers instead of being written and read back
+        if (plan->ops.size() >= 2 && plan->ops[0].type == OP_INIT_UNIFORM &&
+            plan->ops[1].type == OP_REGTILE) {
+            RTHeader *h = reinterpret_cast<RTHeader *>(plan->prog.data() + plan->ops[1].prog_off);
+            h->gen_n = rq.n;
+            plan->ops[1].bytes = state_bytes(rq.n, rq.dtype);
+            plan->ops.erase(plan->ops.begin());
+        }
     } else {
         fold_diagonals(&g, rq.n);
         int kmax = rq.k_max > 0 ? std::min(rq.k_max, 5) : 4;
@@ -873,9 +937,10 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
                     if (!B->diag)
                         for (int q : B->qubits)
                             if (q >= LANE_BITS) tile.push_back(q);
-                int m = std::max(LANE_BITS + (int)tile.size(), std::min(10, rq.n));
+                // tiles of at least 2^12 (2^11 in complex128) amplitudes
+                int m = std::max(LANE_BITS + (int)tile.size(), std::min(rq.dtype == SV_C64 ? 12 : 11, rq.n));
                 m = std::min(m, rq.n);
-                emit_ldstile(g, grp, tile, m, rq.n, rq.dtype, plan);
+                emit_ldstile(g, grp, tile, m, rq.n, rq.dtype, plan, rq.no_mfma);
             }
         } else {
             int m = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 12 : 11);
@@ -888,7 +953,7 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
             for (const Sweep &sw : sweeps) {
                 std::vector<const Block *> items;
                 for (int i : sw.items) items.push_back(&blocks[i]);
-                emit_ldstile(g, items, sw.tile, m, rq.n, rq.dtype, plan);
+                emit_ldstile(g, items, sw.tile, m, rq.n, rq.dtype, plan, rq.no_mfma);
             }
         }
     }
@@ -899,16 +964,6 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
         plan->bytes += op.bytes;
     }
     return SV_OK;
-}
-
-static std::vector<Sweep> regtile_sweeps(const std::vector<SGate> &g, int n, int vb) {
-    return group_sweeps(
-        (int)g.size(), n, vb, [&](int i) { return g[i].kind != SG_DENSE; },
-        [&](int i) {
-            std::vector<int> q = {g[i].q0};
-            if (g[i].kind == SG_CZ) q.push_back(g[i].q1);
-            return q;
-        });
 }
 
 sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int checkpoint_c, Plan *plan) {
@@ -947,7 +1002,7 @@ sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int che
     const int nseg = (int)segs.size();
     std::vector<std::vector<RTProgram>> progs(nseg);
     for (int k = 0; k < nseg; k++) {
-        for (const Sweep &sw : regtile_sweeps(segs[k], rq.n, vb)) {
+        for (const Sweep &sw : regtile_sweeps(segs[k], rq.n, vb, rq.dtype)) {
             progs[k].push_back(build_regtile(segs[k], sw, vb, rq.n));
             push_regtile(progs[k].back(), rq.n, rq.dtype, OP_REGTILE, &plan->ops, plan);
         }

@@ -133,10 +133,20 @@ __global__ __launch_bounds__(BLOCK) void k_regtile(cplx<T> *__restrict__ psi,
 #pragma unroll
     for (int i = 0; i < VB; i++) bq[i] = 1ull << rq[i];
 
+    // uniform row pointer (scalar registers) + lane index: one address
+    // register per lane instead of one 64-bit address per amplitude
     cplx<T> a[NR];
-    const cplx<T> *src = psi + base + lane;
+    const int gen_n = h->gen_n;
+    if (gen_n > 0) {
+        // the Hadamard layer on |0..0>: every amplitude is 2^{-n/2}
+        T v = (T)ldexp(1.0, -(gen_n / 2));
+        if (gen_n & 1) v *= (T)0.70710678118654752440;
 #pragma unroll
-    for (int r = 0; r < NR; r++) a[r] = src[reg_offset<VB>(bq, r)];
+        for (int r = 0; r < NR; r++) { a[r].re = v; a[r].im = (T)0; }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) a[r] = uniform_ptr(psi + (base + reg_offset<VB>(bq, r)))[lane];
+    }
 
     const RTOp *ops = reinterpret_cast<const RTOp *>(prog + h->op_off);
     const DiagTerm *terms = reinterpret_cast<const DiagTerm *>(prog + h->term_off);
@@ -193,9 +203,8 @@ __global__ __launch_bounds__(BLOCK) void k_regtile(cplx<T> *__restrict__ psi,
             a[r].im *= rs;
         }
     }
-    cplx<T> *dst = psi + base + lane;
 #pragma unroll
-    for (int r = 0; r < NR; r++) dst[reg_offset<VB>(bq, r)] = a[r];
+    for (int r = 0; r < NR; r++) uniform_ptr(psi + (base + reg_offset<VB>(bq, r)))[lane] = a[r];
 }
 
 // ---------------------------------------------------------------------------
@@ -249,7 +258,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // 0..15 (one M block); K = 5 needs a second M block for amplitudes 16..31.
 template <int K, int MB>
 __device__ __forceinline__ void block_mfma(cplx<float> *lds, const LTOp &op,
-                                           const cplx<float> *__restrict__ U) {
+                                           const float *__restrict__ F) {
     constexpr int D = 1 << K;
     constexpr int NMB = D / 16;                       // M blocks of 32 real rows
     constexpr int NCOL = (1 << MB) >> K;
@@ -265,18 +274,13 @@ __device__ __forceinline__ void block_mfma(cplx<float> *lds, const LTOp &op,
     off[0] = 0;
 #pragma unroll
     for (int s = 1; s < D; s++) off[s] = off[s & (s - 1)] | (1u << pos[__builtin_ctz(s)]);
-    // A fragments: lane holds E[row = l32 + 32 mb][2 b + half]
+    // A fragments, stored by the planner in lane order: lane holds
+    // E[row = l32 + 32 mb][2 b + half]
     float afrag[NMB][D];
 #pragma unroll
-    for (int mb = 0; mb < NMB; mb++) {
-        const int row = l32 + 32 * mb;
-        const int ao = row >> 1, ra = row & 1;
+    for (int mb = 0; mb < NMB; mb++)
 #pragma unroll
-        for (int b = 0; b < D; b++) {
-            cplx<float> u = U[ao * D + b];
-            afrag[mb][b] = (ra == half) ? u.re : (ra == 0 ? -u.im : u.im);
-        }
-    }
+        for (int b = 0; b < D; b++) afrag[mb][b] = F[(mb * D + b) * 64 + lane];
     for (int ch = wave; ch < NCHUNK; ch += BLOCK / 64) {
         uint32_t base = (uint32_t)(ch * 32 + l32);
 #pragma unroll
@@ -316,20 +320,29 @@ __device__ __forceinline__ void block_mfma(cplx<float> *lds, const LTOp &op,
     }
 }
 
-template <typename T, int MB>
+template <typename T, int MB, int KMAX>
 __device__ __forceinline__ void run_block(cplx<T> *lds, const LTOp &op, const uint8_t *hdr) {
     const cplx<T> *U = reinterpret_cast<const cplx<T> *>(hdr + op.mat_off);
+    const float *F = reinterpret_cast<const float *>(hdr + op.mat_off);
     switch (op.k) {
     case 1: block_valu<T, 1, MB>(lds, op, U); break;
     case 2: block_valu<T, 2, MB>(lds, op, U); break;
     case 3: block_valu<T, 3, MB>(lds, op, U); break;
-    case 4:
-        if constexpr (sizeof(T) == 4 && MB >= 9) block_mfma<4, MB>(lds, op, U);
-        else block_valu<T, 4, MB>(lds, op, U);
+    case 4:   // op.mfma: the plan chose the matrix cores for this block
+        if constexpr (KMAX >= 4) {
+            if constexpr (sizeof(T) == 4 && MB >= 9) {
+                if (op.mfma) { block_mfma<4, MB>(lds, op, F); break; }
+            }
+            block_valu<T, 4, MB>(lds, op, U);
+        }
         break;
     default:
-        if constexpr (sizeof(T) == 4 && MB >= 10) block_mfma<5, MB>(lds, op, U);
-        else if constexpr (MB >= 5) block_valu<T, 5, MB>(lds, op, U);
+        if constexpr (KMAX >= 5) {
+            if constexpr (sizeof(T) == 4 && MB >= 10) {
+                if (op.mfma) { block_mfma<5, MB>(lds, op, F); break; }
+            }
+            block_valu<T, 5, MB>(lds, op, U);
+        }
         break;
     }
 }
@@ -366,7 +379,7 @@ __device__ __forceinline__ void diag_regs(cplx<T> (&v)[PER], const LTOp &op, con
     }
 }
 
-template <typename T, int MB>
+template <typename T, int MB, int KMAX>
 __global__ __launch_bounds__(BLOCK) void k_ldstile(cplx<T> *__restrict__ psi,
                                                    const uint8_t *__restrict__ prog,
                                                    uint64_t ntiles) {
@@ -417,7 +430,7 @@ __global__ __launch_bounds__(BLOCK) void k_ldstile(cplx<T> *__restrict__ psi,
         for (int o = first; o <= last; o++) {
             const LTOp &op = ops[o];
             if (op.kind == LT_BLOCK) {
-                run_block<T, MB>(lds, op, prog);
+                run_block<T, MB, KMAX>(lds, op, prog);
             } else {
 #pragma unroll
                 for (int i = 0; i < PER; i++) v[i] = lds[t + BLOCK * i];
@@ -500,13 +513,20 @@ static sv_status launch_typed(sv_state *st, const Plan &plan, const Op &op, cplx
         const uint8_t *prog = (const uint8_t *)plan.dprog + op.prog_off;
         const uint64_t ntiles = N >> op.vbits;
         const unsigned grid = (unsigned)ntiles;
-#define LT_CASE(MB) \
-    case MB: hipLaunchKernelGGL((k_ldstile<T, MB>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles); break;
+        // kernel variant by tile width and widest block (k <= 3 variants
+        // carry fewer registers)
+        const bool wide = op.q1 > 3;
+#define LT_CASE(MB)                                                                                       \
+    case MB:                                                                                              \
+        if (wide) hipLaunchKernelGGL((k_ldstile<T, MB, 5>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles); \
+        else hipLaunchKernelGGL((k_ldstile<T, MB, 3>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles);      \
+        break;
         switch (op.vbits) {
             LT_CASE(8) LT_CASE(9) LT_CASE(10) LT_CASE(11) LT_CASE(12)
         case 13:
             if constexpr (sizeof(T) == 4) {
-                hipLaunchKernelGGL((k_ldstile<T, 13>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles);
+                if (wide) hipLaunchKernelGGL((k_ldstile<T, 13, 5>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles);
+                else hipLaunchKernelGGL((k_ldstile<T, 13, 3>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles);
                 break;
             }
             return fail(SV_EINVAL, "LDS tile too large for complex128");

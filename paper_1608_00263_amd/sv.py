@@ -87,6 +87,8 @@ EXPORTS = {
     "sv_apply_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "sv_last_error": (ctypes.c_char_p, []),
+    "sv_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                   ctypes.c_void_p]),
     "sv_apply_circuit_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p]),
@@ -145,11 +147,12 @@ class CircuitArgs:
 
 
 FLAG_FROM_ZERO = 1
+FLAG_NO_MFMA = 2
 
 
-def make_opts(mode="auto", k_max=0, tile=0, from_zero=False) -> Opts:
+def make_opts(mode="auto", k_max=0, tile=0, from_zero=False, no_mfma=False) -> Opts:
     m = MODES[mode] if isinstance(mode, str) else int(mode)
-    return Opts(m, k_max, tile, FLAG_FROM_ZERO if from_zero else 0)
+    return Opts(m, k_max, tile, (FLAG_FROM_ZERO if from_zero else 0) | (FLAG_NO_MFMA if no_mfma else 0))
 
 
 def _stream_handle(torch):
@@ -189,10 +192,10 @@ class State:
         check(lib().sv_reset(self.h))
 
     def apply(self, circ, mode="auto", k_max=0, tile=0, args: Optional[CircuitArgs] = None,
-              from_zero=False):
+              from_zero=False, no_mfma=False):
         """Apply circ in place (from |0..0> regardless of contents if from_zero)."""
         a = args or CircuitArgs(circ)
-        o = make_opts(mode, k_max, tile, from_zero)
+        o = make_opts(mode, k_max, tile, from_zero, no_mfma)
         check(lib().sv_apply_circuit(self.h, a.ref, ctypes.byref(o)))
 
     def apply_timed(self, circ, mode="auto", k_max=0, tile=0, args: Optional[CircuitArgs] = None,
@@ -210,9 +213,18 @@ class State:
         m = min(n.value, cap)
         return ms[:m], kinds[:m], by[:m]
 
-    def plan_info(self, circ, mode="auto", k_max=0, tile=0):
+    def autotune(self, circ, from_zero=True):
+        """Run the autotuner for circ; returns (mode name, k_max, tile, complete)."""
         a = CircuitArgs(circ)
-        o = make_opts(mode, k_max, tile)
+        o = Opts()
+        done = ctypes.c_int()
+        check(lib().sv_autotune(self.h, a.ref, 1 if from_zero else 0, ctypes.byref(o), ctypes.byref(done)))
+        name = {v: k for k, v in MODES.items()}[o.mode]
+        return name, o.k_max, o.tile_qubits, bool(done.value)
+
+    def plan_info(self, circ, mode="auto", k_max=0, tile=0, no_mfma=False):
+        a = CircuitArgs(circ)
+        o = make_opts(mode, k_max, tile, no_mfma=no_mfma)
         sw = ctypes.c_int64()
         by = ctypes.c_double()
         check(lib().sv_plan_info(self.h, a.ref, ctypes.byref(o), ctypes.byref(sw), ctypes.byref(by)))
