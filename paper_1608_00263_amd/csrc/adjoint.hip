@@ -25,74 +25,135 @@
 namespace svi {
 
 template <typename T>
-__device__ __forceinline__ double re_conj_mul(cplx<T> mu, cplx<T> v) {
-    return (double)mu.re * (double)v.re + (double)mu.im * (double)v.im;
-}
-
-template <typename T>
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
     return v;
 }
 
-// sum over this lane's registers of Re conj(mu) (D phi), D on register slot S
-template <typename T, int NR, int S>
-__device__ __forceinline__ double grad_reg(const cplx<T> (&phi)[NR], const cplx<T> (&mu)[NR],
-                                           const Mat2<T> &d) {
-    double acc = 0;
+// Im conj(a) b and Re conj(a) b
+template <typename T>
+__device__ __forceinline__ T im_cm(cplx<T> a, cplx<T> b) { return fma(a.re, b.im, -a.im * b.re); }
+template <typename T>
+__device__ __forceinline__ T re_cm(cplx<T> a, cplx<T> b) { return fma(a.re, b.re, a.im * b.im); }
+
+// This lane's share of Re <mu| D |phi> for D on register slot S.  Closed
+// forms for the generators of the parametrised gates (pairs (0, 1) of the
+// slot): RX: D = -(i/2) X gives (1/2) [Im conj(mu0) phi1 + Im conj(mu1) phi0];
+// RY: D = -(i/2) Y gives (1/2) [Re conj(mu1) phi0 - Re conj(mu0) phi1];
+// phase: D = i|1><1| gives -Im conj(mu1) phi1.
+template <typename T, int NR, int S, int G>
+__device__ __forceinline__ double grad_reg_g(const cplx<T> (&phi)[NR], const cplx<T> (&mu)[NR],
+                                             const Mat2<T> &d) {
+    if constexpr (G == G_GEN) {
+        double acc = 0;
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        if (r & (1 << S)) continue;
-        const int r1 = r | (1 << S);
-        cplx<T> d0 = cmad(d.m[1], phi[r1], cmul(d.m[0], phi[r]));
-        cplx<T> d1 = cmad(d.m[3], phi[r1], cmul(d.m[2], phi[r]));
-        acc += re_conj_mul(mu[r], d0) + re_conj_mul(mu[r1], d1);
+        for (int r = 0; r < NR; r++) {
+            if (r & (1 << S)) continue;
+            const int r1 = r | (1 << S);
+            cplx<T> d0 = cmad(d.m[1], phi[r1], cmul(d.m[0], phi[r]));
+            cplx<T> d1 = cmad(d.m[3], phi[r1], cmul(d.m[2], phi[r]));
+            acc += (double)re_cm(mu[r], d0) + (double)re_cm(mu[r1], d1);
+        }
+        return acc;
+    } else {
+        T acc = 0;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (r & (1 << S)) continue;
+            const int r1 = r | (1 << S);
+            if constexpr (G == G_RX) acc += im_cm(mu[r], phi[r1]) + im_cm(mu[r1], phi[r]);
+            else if constexpr (G == G_RY) acc += re_cm(mu[r1], phi[r]) - re_cm(mu[r], phi[r1]);
+            else acc -= im_cm(mu[r1], phi[r1]);
+        }
+        return (G == G_P ? 1.0 : 0.5) * (double)acc;
     }
-    return acc;
+}
+
+template <typename T, int NR, int S>
+__device__ __forceinline__ double grad_reg_s(const cplx<T> (&phi)[NR], const cplx<T> (&mu)[NR],
+                                             const Mat2<T> &d, int g) {
+    switch (g) {
+    case G_RX: return grad_reg_g<T, NR, S, G_RX>(phi, mu, d);
+    case G_RY: return grad_reg_g<T, NR, S, G_RY>(phi, mu, d);
+    case G_P: return grad_reg_g<T, NR, S, G_P>(phi, mu, d);
+    default: return grad_reg_g<T, NR, S, G_GEN>(phi, mu, d);
+    }
 }
 
 template <typename T, int NR>
 __device__ __forceinline__ double grad_reg_dispatch(const cplx<T> (&phi)[NR], const cplx<T> (&mu)[NR],
-                                                    const Mat2<T> &d, int s) {
+                                                    const Mat2<T> &d, int s, int g) {
     switch (s) {
-    case 0: return grad_reg<T, NR, 0>(phi, mu, d);
-    case 1: if constexpr (NR > 2) return grad_reg<T, NR, 1>(phi, mu, d); break;
-    case 2: if constexpr (NR > 4) return grad_reg<T, NR, 2>(phi, mu, d); break;
-    case 3: if constexpr (NR > 8) return grad_reg<T, NR, 3>(phi, mu, d); break;
-    case 4: if constexpr (NR > 16) return grad_reg<T, NR, 4>(phi, mu, d); break;
+    case 0: return grad_reg_s<T, NR, 0>(phi, mu, d, g);
+    case 1: if constexpr (NR > 2) return grad_reg_s<T, NR, 1>(phi, mu, d, g); break;
+    case 2: if constexpr (NR > 4) return grad_reg_s<T, NR, 2>(phi, mu, d, g); break;
+    case 3: if constexpr (NR > 8) return grad_reg_s<T, NR, 3>(phi, mu, d, g); break;
+    case 4: if constexpr (NR > 16) return grad_reg_s<T, NR, 4>(phi, mu, d, g); break;
     default: break;
     }
     return 0.0;
 }
 
-template <typename T, int NR, int B>
-__device__ __forceinline__ double grad_lane(const cplx<T> (&phi)[NR], const cplx<T> (&mu)[NR],
-                                            const Mat2<T> &d, int lane) {
+// The same for D on lane bit B: the pair partner lives in the lane whose
+// bit B differs (hi = this lane's bit).
+template <typename T, int NR, int B, int G>
+__device__ __forceinline__ double grad_lane_g(const cplx<T> (&phi)[NR], const cplx<T> (&mu)[NR],
+                                              const Mat2<T> &d, int lane) {
     const bool hi = (lane >> B) & 1;
-    cplx<T> cs = hi ? d.m[3] : d.m[0];
-    cplx<T> cp = hi ? d.m[2] : d.m[1];
-    double acc = 0;
+    if constexpr (G == G_P) {
+        T acc = 0;
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        cplx<T> p;
-        p.re = lane_xor<B>(phi[r].re);
-        p.im = lane_xor<B>(phi[r].im);
-        acc += re_conj_mul(mu[r], cmad(cp, p, cmul(cs, phi[r])));
+        for (int r = 0; r < NR; r++) acc -= im_cm(mu[r], phi[r]);
+        return hi ? (double)acc : 0.0;
+    } else if constexpr (G == G_GEN) {
+        cplx<T> cs = hi ? d.m[3] : d.m[0];
+        cplx<T> cp = hi ? d.m[2] : d.m[1];
+        double acc = 0;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cplx<T> p;
+            p.re = lane_xor<B>(phi[r].re);
+            p.im = lane_xor<B>(phi[r].im);
+            acc += (double)re_cm(mu[r], cmad(cp, p, cmul(cs, phi[r])));
+        }
+        return acc;
+    } else {
+        T acc = 0;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cplx<T> p;
+            p.re = lane_xor<B>(phi[r].re);
+            p.im = lane_xor<B>(phi[r].im);
+            if constexpr (G == G_RX) acc += im_cm(mu[r], p);
+            else acc += re_cm(mu[r], p);
+        }
+        if constexpr (G == G_RY) acc = hi ? acc : -acc;
+        return 0.5 * (double)acc;
     }
-    return acc;
+}
+
+template <typename T, int NR, int B>
+__device__ __forceinline__ double grad_lane_b(const cplx<T> (&phi)[NR], const cplx<T> (&mu)[NR],
+                                              const Mat2<T> &d, int lane, int g) {
+    switch (g) {
+    case G_RX: return grad_lane_g<T, NR, B, G_RX>(phi, mu, d, lane);
+    case G_RY: return grad_lane_g<T, NR, B, G_RY>(phi, mu, d, lane);
+    case G_P: return grad_lane_g<T, NR, B, G_P>(phi, mu, d, lane);
+    default: return grad_lane_g<T, NR, B, G_GEN>(phi, mu, d, lane);
+    }
 }
 
 template <typename T, int NR>
 __device__ __forceinline__ double grad_lane_dispatch(const cplx<T> (&phi)[NR], const cplx<T> (&mu)[NR],
-                                                     const Mat2<T> &d, int b, int lane) {
+                                                     const Mat2<T> &d, int b, int lane, int g) {
     switch (b) {
-    case 0: return grad_lane<T, NR, 0>(phi, mu, d, lane);
-    case 1: return grad_lane<T, NR, 1>(phi, mu, d, lane);
-    case 2: return grad_lane<T, NR, 2>(phi, mu, d, lane);
-    case 3: return grad_lane<T, NR, 3>(phi, mu, d, lane);
-    case 4: return grad_lane<T, NR, 4>(phi, mu, d, lane);
-    default: return grad_lane<T, NR, 5>(phi, mu, d, lane);
+    case 0: return grad_lane_b<T, NR, 0>(phi, mu, d, lane, g);
+    case 1: return grad_lane_b<T, NR, 1>(phi, mu, d, lane, g);
+    case 2: return grad_lane_b<T, NR, 2>(phi, mu, d, lane, g);
+    case 3: return grad_lane_b<T, NR, 3>(phi, mu, d, lane, g);
+    case 4: return grad_lane_b<T, NR, 4>(phi, mu, d, lane, g);
+    default: return grad_lane_b<T, NR, 5>(phi, mu, d, lane, g);
     }
 }
 
@@ -131,8 +192,9 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
         if (kind == RT_REG || kind == RT_LANE) {
             if (slot >= 0) {
                 const Mat2<T> d = load_mat<T>(ops[o].d);
-                double g = kind == RT_REG ? grad_reg_dispatch<T, NR>(phi, mu, d, arg)
-                                          : grad_lane_dispatch<T, NR>(phi, mu, d, arg, lane);
+                const int gk = ops[o].gkind;
+                double g = kind == RT_REG ? grad_reg_dispatch<T, NR>(phi, mu, d, arg, gk)
+                                          : grad_lane_dispatch<T, NR>(phi, mu, d, arg, lane, gk);
                 g = wave_sum_d<T>(g);
                 if (lane == 0) gpart[tile * (uint64_t)nslots + slot] = g;
             }
@@ -173,7 +235,7 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
                 double g = 0;
 #pragma unroll
                 for (int r = 0; r < NR; r++)
-                    if ((rs >> r) & 1) g += re_conj_mul(mu[r], cmul(dv, phi[r]));
+                    if ((rs >> r) & 1) g += (double)re_cm(mu[r], cmul(dv, phi[r]));
                 g = wave_sum_d<T>(g);
                 if (lane == 0) gpart[tile * (uint64_t)nslots + slot] = g;
             }

@@ -100,6 +100,17 @@ __device__ __forceinline__ void pair_form(cplx<T> &x, cplx<T> &y, const Mat2<T> 
     } else if constexpr (FORM == F_SXDG) {     // x + i y, i x + y
         x.re = a.re - b.im; x.im = a.im + b.re;
         y.re = b.re - a.im; y.im = b.im + a.re;
+    } else if constexpr (FORM == F_RX) {       // c x - i s y, -i s x + c y
+        const T c = u.m[0].re, sn = -u.m[1].im;
+        x.re = fma(c, a.re, sn * b.im); x.im = fma(c, a.im, -sn * b.re);
+        y.re = fma(c, b.re, sn * a.im); y.im = fma(c, b.im, -sn * a.re);
+    } else if constexpr (FORM == F_RY) {       // c x - s y, s x + c y
+        const T c = u.m[0].re, sn = u.m[2].re;
+        x.re = fma(c, a.re, -sn * b.re); x.im = fma(c, a.im, -sn * b.im);
+        y.re = fma(c, b.re, sn * a.re); y.im = fma(c, b.im, sn * a.im);
+    } else if constexpr (FORM == F_REAL) {
+        x.re = fma(u.m[0].re, a.re, u.m[1].re * b.re); x.im = fma(u.m[0].re, a.im, u.m[1].re * b.im);
+        y.re = fma(u.m[2].re, a.re, u.m[3].re * b.re); y.im = fma(u.m[2].re, a.im, u.m[3].re * b.im);
     } else {                                   // F_PHASE
         y = cmul(u.m[3], b);
     }
@@ -123,6 +134,9 @@ __device__ __forceinline__ void reg_gate_s(cplx<T> (&a)[NR], const Mat2<T> &u, i
     case F_SXDG: reg_gate_f<T, NR, S, F_SXDG>(a, u); break;
     case F_SYDG: reg_gate_f<T, NR, S, F_SYDG>(a, u); break;
     case F_PHASE: reg_gate_f<T, NR, S, F_PHASE>(a, u); break;
+    case F_RX: reg_gate_f<T, NR, S, F_RX>(a, u); break;
+    case F_RY: reg_gate_f<T, NR, S, F_RY>(a, u); break;
+    case F_REAL: reg_gate_f<T, NR, S, F_REAL>(a, u); break;
     default: reg_gate_f<T, NR, S, F_GEN>(a, u); break;
     }
 }
@@ -154,10 +168,19 @@ __device__ __forceinline__ void lane_gate_f(cplx<T> (&a)[NR], const Mat2<T> &u, 
         return;
     }
     cplx<T> cs, cp;
-    T sg = (T)1;
+    T sg = (T)1, rc = (T)0, rs = (T)0;
     if constexpr (FORM == F_GEN) {
         cs = hi ? u.m[3] : u.m[0];
         cp = hi ? u.m[2] : u.m[1];
+    } else if constexpr (FORM == F_RX) {
+        rc = u.m[0].re;
+        rs = -u.m[1].im;            // self c - i s p (both halves)
+    } else if constexpr (FORM == F_RY) {
+        rc = u.m[0].re;
+        rs = hi ? u.m[2].re : -u.m[2].re;   // lo: c self - s p, hi: c self + s p
+    } else if constexpr (FORM == F_REAL) {
+        rc = hi ? u.m[3].re : u.m[0].re;
+        rs = hi ? u.m[2].re : u.m[1].re;    // cs self + cp p
     } else if constexpr (FORM == F_H) {
         sg = hi ? (T)-1 : (T)1;     // lo: self + p, hi: p - self
     } else if constexpr (FORM == F_SY) {
@@ -179,8 +202,12 @@ __device__ __forceinline__ void lane_gate_f(cplx<T> (&a)[NR], const Mat2<T> &u, 
             o.re = fma(sg, p.re, s.re); o.im = fma(sg, p.im, s.im);
         } else if constexpr (FORM == F_SX) {    // self - i p (both halves)
             o.re = s.re + p.im; o.im = s.im - p.re;
-        } else {                                 // F_SXDG: self + i p
+        } else if constexpr (FORM == F_SXDG) {  // self + i p
             o.re = s.re - p.im; o.im = s.im + p.re;
+        } else if constexpr (FORM == F_RX) {
+            o.re = fma(rc, s.re, rs * p.im); o.im = fma(rc, s.im, -rs * p.re);
+        } else {                                 // F_RY, F_REAL
+            o.re = fma(rc, s.re, rs * p.re); o.im = fma(rc, s.im, rs * p.im);
         }
         a[r] = o;
     }
@@ -195,6 +222,9 @@ __device__ __forceinline__ void lane_gate_b(cplx<T> (&a)[NR], const Mat2<T> &u, 
     case F_SXDG: lane_gate_f<T, NR, B, F_SXDG>(a, u, lane); break;
     case F_SYDG: lane_gate_f<T, NR, B, F_SYDG>(a, u, lane); break;
     case F_PHASE: lane_gate_f<T, NR, B, F_PHASE>(a, u, lane); break;
+    case F_RX: lane_gate_f<T, NR, B, F_RX>(a, u, lane); break;
+    case F_RY: lane_gate_f<T, NR, B, F_RY>(a, u, lane); break;
+    case F_REAL: lane_gate_f<T, NR, B, F_REAL>(a, u, lane); break;
     default: lane_gate_f<T, NR, B, F_GEN>(a, u, lane); break;
     }
 }

@@ -67,7 +67,6 @@ enum RTKind : int32_t {
     RT_LANE = 2,    // dense 2x2 on lane bit a (cross-lane shuffles)
     RT_SIGNS = 3,   // nterms sign flips (CZ) starting at term index a
     RT_PHASE = 4,   // one general diagonal phase term (index a)
-    RT_GRAD = 5,    // adjoint: inner product with a derivative generator
 };
 
 // Arithmetic forms of a single-qubit gate inside a register tile.  The
@@ -81,7 +80,17 @@ enum RTForm : int32_t {
     F_SXDG = 4,     // [[1, i], [i, 1]]
     F_SYDG = 5,     // [[1, 1], [-1, 1]]
     F_PHASE = 6,    // diag(1, u[3])
+    F_RX = 7,       // [[c, -i s], [-i s, c]]   (c = u00, s = -Im u01)
+    F_RY = 8,       // [[c, -s], [s, c]]         (c = u00, s = u10)
+    F_REAL = 9,     // real 2x2 matrix
 };
+
+// True for the forms that carry a factor sqrt2.
+inline bool form_scaled(int f) { return f >= F_H && f <= F_SYDG; }
+
+// Derivative generators with closed-form gradient terms (dU = D U):
+// D = -(i/2) X for RX, -(i/2) Y for RY, i |1><1| for the phase gate.
+enum GradKind : int32_t { G_GEN = 0, G_RX = 1, G_RY = 2, G_P = 3 };
 
 struct RTOp {               // 160 bytes
     int32_t kind;
@@ -91,7 +100,8 @@ struct RTOp {               // 160 bytes
     double u[8];            // 2x2 complex (re, im) row-major
     double d[8];            // adjoint: derivative generator D (dU = D U)
     int32_t form;           // RTForm
-    int32_t pad[3];
+    int32_t gkind;          // GradKind of the generator
+    int32_t pad[2];
 };
 
 // A diagonal term: amplitude x is multiplied by `val` (or negated for
@@ -208,6 +218,7 @@ struct SGate {
     int slot = -1;   // parametrised gate: its gradient slot (list order)
     M2 d{};          // derivative generator of a parametrised gate
     int form = 0;    // RTForm of the exact gate (F_GEN once altered)
+    int gkind = 0;   // GradKind of a parametrised gate
 };
 
 struct PlanRequest {

@@ -168,10 +168,20 @@ sv_status specialise(const sv_circuit *c, int n, std::vector<SGate> *out) {
             default: break;
             }
         }
+        if (s.form == F_GEN && s.kind == SG_DENSE) {
+            // rotation structure (cos/sin forms) and real matrices
+            const bool rx = g.kind == SV_SX || g.kind == SV_SXDG;
+            const bool ry = g.kind == SV_SY || g.kind == SV_SYDG;
+            if (rx) s.form = F_RX;
+            else if (ry) s.form = F_RY;
+            else if (is_real(s.u)) s.form = F_REAL;
+        }
         if (s.kind == SG_DIAG1 && s.u.m[0].re == 1.0 && s.u.m[0].im == 0.0) s.form = F_PHASE;
         if (g.param >= 0) {
             s.slot = nslot++;
             derivative_generator(g.kind, &s.d);
+            s.gkind = (g.kind == SV_SX || g.kind == SV_SXDG) ? G_RX
+                    : (g.kind == SV_SY || g.kind == SV_SYDG) ? G_RY : G_P;
         }
         out->push_back(s);
     }
@@ -208,10 +218,10 @@ void fold_diagonals(std::vector<SGate> *gl, int n, bool param_safe, bool keep_ch
             }
             if (target < 0) continue;   // no dense gate on q: stays a phase
             // a gate with an add-only form costs less kept apart from the phase
-            if (keep_cheap && g[target].form != F_GEN) continue;
+            if (keep_cheap && form_scaled(g[target].form)) continue;
             M2 d = g[i].u;
             g[target].u = before ? m2_mul(g[target].u, d) : m2_mul(d, g[target].u);
-            g[target].form = F_GEN;
+            g[target].form = is_real(g[target].u) ? F_REAL : F_GEN;
             dead[i] = 1;
         }
     }
@@ -448,9 +458,15 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
             o.slot = s.slot;
             put_mat(o.d, s.d);
             o.form = s.form;
-            if (s.kind == SG_DENSE && s.form != F_GEN) {
-                if (cheap) nc++;
-                else o.form = F_GEN;
+            o.gkind = s.gkind;
+            if (s.kind == SG_DENSE && form_scaled(s.form)) {
+                if (cheap) {
+                    nc++;
+                } else {
+                    // unscaled equivalents of the add-only forms
+                    o.form = (s.form == F_SX || s.form == F_SXDG) ? F_RX
+                           : (s.form == F_SY || s.form == F_SYDG) ? F_RY : F_REAL;
+                }
             }
             ops.push_back(o);
         } else if (s.kind == SG_CZ) {
@@ -481,6 +497,7 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
             o.a = (int)terms.size();
             o.nterms = 1;
             o.slot = s.slot;
+            o.gkind = s.gkind;
             put_mat(o.d, s.d);
             terms.push_back(t);
             ops.push_back(o);
@@ -836,8 +853,9 @@ static std::vector<Sweep> regtile_sweeps(const std::vector<SGate> &g, int n, int
         const bool lane = s.q0 < LANE_BITS;
         const bool reg = !lane && in_tile[s.q0];
         if (s.kind == SG_DIAG1) return reg ? 2.0 : 4.0;
-        const bool cheap = s.form != F_GEN;
-        return lane ? (cheap ? 5.0 : 11.0) : (cheap ? 2.0 : 8.0);
+        if (form_scaled(s.form)) return lane ? 5.0 : 2.0;
+        if (s.form == F_GEN) return lane ? 11.0 : 8.0;
+        return lane ? 7.0 : 4.0;   // rotation and real forms
     };
     return group_sweeps(
         (int)g.size(), n, vb, [&](int i) { return g[i].kind != SG_DENSE; },
@@ -986,8 +1004,8 @@ sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int che
         return fail(SV_EINVAL, "sv_backward: the circuit must open with a Hadamard on every qubit");
     }
     fold_diagonals(&g, rq.n, true);
-    int vb = rq.tile > 0 ? rq.tile : 4;
-    vb = std::max(1, std::min(vb, rq.dtype == SV_C64 ? 5 : 4));
+    int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 4 : 3);
+    vb = std::max(1, std::min(vb, 4));
     vb = std::min(vb, rq.n - LANE_BITS - 2);
     // segments of consecutive gates between checkpoints
     std::vector<std::vector<SGate>> segs(1);
