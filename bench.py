@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-modes", action="store_true", help="skip the per-mode circuit timings")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the ensemble timing")
+    ap.add_argument("--ensemble", type=int, default=512, help="ensemble instances")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -162,6 +164,8 @@ def main():
         out["circuit_s"] = mode_timings(sv, C, circ, torch)
     if not a.no_grad:
         out["grad"] = grad_timings(sv, C, torch)
+    if not a.no_ensemble:
+        out["ensemble"] = ensemble_timings(sv, C, torch, a.ensemble)
     st.close()
     del st
     torch.cuda.empty_cache()
@@ -207,6 +211,49 @@ def mode_timings(sv, C, circ, torch):
         del st
         torch.cuda.empty_cache()
     return res
+
+
+def ensemble_timings(sv, C, torch, count, reps=3):
+    """The ensemble of Sec. IV circuits (grids 4x5, 4x6, 5x5; depth 20..40):
+    one launch per sweep round over all instances (default), the persistent
+    work-queue launch, and the ordinary per-instance launches, each captured
+    in a graph."""
+    import numpy as np
+    circs = C.make_ensemble(count)
+    args = sv.BatchArgs(circs)
+    states = [sv.State(c.n, "c64") for c in circs]
+    state_bytes = sum(8.0 * 2 ** c.n for c in circs)
+    out = {"workload": "%d instances, grids 4x5/4x6/5x5, depth 20..40, complex64, %.1f GB of states"
+                       % (count, state_bytes / 1e9)}
+    runs = [("auto", {}), ("regtile_t4", dict(mode="regtile", tile=4)),
+            ("regtile_t5", dict(mode="regtile", tile=5)),
+            ("persistent_t5", dict(mode="regtile", tile=5, persistent=True)),
+            ("launches_t5", dict(mode="regtile", tile=5, launches=True))]
+    for label, kw in runs:
+        t0 = time.perf_counter()
+        res = sv.apply_batch(states, circs, args=args, **kw)      # plans, width, graph
+        first = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = sv.apply_batch(states, circs, args=args, **kw)
+        dt = (time.perf_counter() - t0) / reps
+        rec = {"s": round(dt, 4), "first_call_s": round(first, 3),
+               "instances_per_s": round(count / dt, 1)}
+        if "tile" in kw:
+            by = sum(sv.host_plan(c, "c64", "regtile", 0, kw["tile"])["bytes"] for c in circs) + state_bytes
+            rec["GBps"] = round(by / dt / 1e9, 1)
+        ent = np.array([r["entropy"] for r in res])
+        norm = np.array([r["norm"] for r in res])
+        rec["max_norm_err"] = float(np.abs(norm - 1).max())
+        rec["mean_entropy_gap"] = float(np.mean([math.log(2.0 ** c.n) - e for c, e in zip(circs, ent)]))
+        out[label] = rec
+        log("ensemble %s: %.3f s (first call %.2f s)" % (label, dt, first))
+    for st in states:
+        st.close()
+    del states
+    torch.cuda.empty_cache()
+    return out
 
 
 def grad_timings(sv, C, torch):

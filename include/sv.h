@@ -101,8 +101,16 @@ enum {
 /* sv_opts.flags bits */
 enum {
     SV_FLAG_FROM_ZERO = 1,  /* ignore the current contents: simulate U|0...0> */
-    SV_FLAG_NO_MFMA = 2     /* fused blocks with k >= 4 on the VALU instead of
+    SV_FLAG_NO_MFMA = 2,    /* fused blocks with k >= 4 on the VALU instead of
                                the matrix cores (for comparison)             */
+    SV_FLAG_STATE_READY = 4,/* sv_backward: the handle already holds U(theta)
+                               |0...0> (sv_apply_circuit of the same circuit
+                               and theta): the forward pass is skipped; only
+                               with checkpoint_c = 0                         */
+    SV_FLAG_BATCH_LAUNCHES = 8, /* sv_apply_batch: one captured graph of the
+                               ordinary per-instance launches (for comparison) */
+    SV_FLAG_BATCH_PERSISTENT = 16 /* sv_apply_batch: the persistent-kernel
+                               schedule instead of one launch per round      */
 };
 
 typedef struct {
@@ -225,8 +233,11 @@ sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k,
  * path) kept at the end of every checkpoint_c-th cycle (0 = none) and
  * reloaded on the way back.  The circuit must open with a Hadamard on every
  * qubit and list its gates in nondecreasing cycle order.  On entry the
- * handle may hold anything; on return its contents are unspecified (the
- * forward state has been uncomputed).  loss gets L(theta).  Uses device
+ * handle may hold anything, unless opts->flags has SV_FLAG_STATE_READY: then
+ * it must hold U(theta)|0...0> already (as left by sv_apply_circuit of the
+ * same circuit), the forward pass is skipped, and checkpoint_c must be 0.
+ * On return its contents are unspecified (the forward state has been
+ * uncomputed).  loss gets L(theta).  Uses device
  * scratch of one extra state plus the checkpoints.  SV_EINVAL if a
  * parametrised gate is not a rotation; SV_ESTATE if a sample has p = 0;
  * SV_ERANGE for n < 8. */
@@ -234,11 +245,29 @@ sv_status sv_backward(sv_state *st, const sv_circuit *c, const sv_opts *opts,
                       const uint64_t *samples, int64_t k, int checkpoint_c,
                       double *loss, double *grad);
 
-/* Ensemble: simulate count independent circuits from |0...0>, each into its
- * own handle sts[i] (sizes may differ), in one persistent kernel launch
- * captured in a HIP graph and replayed, then write each instance's
- * statistics to out[i].  All handles must share one dtype and stream.
- * Synchronises. */
+/* Ensemble (the statistics of Sec. IV are averages over many random circuit
+ * instances): simulate count independent circuits from |0...0>, each into
+ * its own handle sts[i] (sizes and depths may differ), and write each
+ * instance's statistics to out[i].  All handles must share one dtype and
+ * stream; opts may be NULL (SV_MODE_AUTO).  Synchronises.
+ *
+ * Complex64 ensembles whose instances have n >= 14 and whose plans consist
+ * of register-tile sweeps only (SV_MODE_AUTO or SV_MODE_REGTILE) are cut into
+ * work items (16 register tiles of one sweep of one instance, or 2^14
+ * amplitudes of one instance's statistics) ordered by sweep round, then
+ * instance.  By default each round is one launch over the items of every
+ * instance (the sweeps of all instances fill the GPU together);
+ * SV_FLAG_BATCH_PERSISTENT runs the same table in one persistent launch
+ * whose workgroups take items from a global queue and wait on per-instance
+ * completion counters.  Either schedule is captured in a HIP graph that is
+ * kept and replayed while the same handles, circuits and options come again
+ * (one such graph per process).  The register-tile width is tile_qubits
+ * (clamped to 3..5) under SV_MODE_REGTILE, else timed once on the largest
+ * instance.  Everything else (complex128, other modes, smaller instances,
+ * SV_FLAG_BATCH_LAUNCHES) runs as one captured graph of the ordinary
+ * per-sweep launches.  SV_EDEVICE if a dependency wait of the persistent
+ * kernel exceeds its bound (the kernel still drains and exits; the states
+ * are then unspecified). */
 sv_status sv_apply_batch(sv_state **sts, const sv_circuit *cs, int64_t count,
                          const sv_opts *opts, sv_stats *out);
 

@@ -1,0 +1,69 @@
+"""PyTorch autograd binding of the adjoint gradient.
+
+The loss is the sample cross entropy of Eqs. (ae) and (5),
+L(theta) = ln S - (1/k) sum_i ln p_theta(x_i), for a circuit whose
+parametrised gates are rotations exp(-i theta_j G_j / 2) (Sec. V): the
+forward runs the circuit on the GPU and evaluates the cross entropy; the
+backward runs the library's adjoint pass on the output state the forward
+left behind, so the state is computed once per step.  For a unitary circuit
+S = 1, so the gradient is that of -(1/k) sum ln p_theta(x_i).
+
+Argument marshalling only: both passes are calls of the C library.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import sv
+
+
+class _CircuitCrossEntropy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta, circ, state, samples, checkpoint_c):
+        c = circ.with_theta(theta.detach().to("cpu", torch.float64).numpy())
+        state.apply(c, "auto", from_zero=True)
+        ce, _, zeros = state.cross_entropy(samples)
+        if zeros:
+            raise sv.SVError(sv.SV_ESTATE, "a sample has probability 0 under the circuit")
+        ctx.circ = c
+        ctx.state = state
+        ctx.samples = samples
+        ctx.checkpoint_c = checkpoint_c
+        ctx.theta_meta = (theta.dtype, theta.device)
+        return torch.tensor(ce, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, g):
+        ready = ctx.checkpoint_c == 0
+        _, grad = ctx.state.backward(ctx.circ, ctx.samples, checkpoint_c=ctx.checkpoint_c,
+                                     state_ready=ready)
+        dtype, device = ctx.theta_meta
+        gt = torch.from_numpy(np.asarray(grad, dtype=np.float64)).to(device=device, dtype=dtype)
+        return g.to(device=device, dtype=dtype) * gt, None, None, None, None
+
+
+class CircuitCrossEntropy(torch.nn.Module):
+    """theta -> L(theta) on fixed samples, differentiable by the adjoint method.
+
+    circ: a parametrised circuit (its theta is replaced by the input);
+    samples: uint64 bit-strings; checkpoint_c: 0 reuses the forward state for
+    the backward pass, c > 0 recomputes it with a state copy kept every c
+    cycles.  The module owns one GPU state of the circuit's size.
+    """
+
+    def __init__(self, circ, samples, dtype: str = "c64", checkpoint_c: int = 0):
+        super().__init__()
+        self.circ = circ
+        self.samples = np.ascontiguousarray(samples, dtype=np.uint64)
+        self.checkpoint_c = int(checkpoint_c)
+        self.state = sv.State(circ.n, dtype)
+
+    def forward(self, theta: torch.Tensor) -> torch.Tensor:
+        if theta.numel() != self.circ.nparams:
+            raise ValueError("theta has %d entries, the circuit %d parameters"
+                             % (theta.numel(), self.circ.nparams))
+        return _CircuitCrossEntropy.apply(theta, self.circ, self.state, self.samples, self.checkpoint_c)
+
+    def close(self):
+        self.state.close()

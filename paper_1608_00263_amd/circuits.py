@@ -316,3 +316,22 @@ def random_probabilities(N: int, seed: int, zeros: int = 0) -> np.ndarray:
     if zeros:
         p[rs.choice(N, size=min(zeros, N - 1), replace=False)] = 0.0
     return p / p.sum()
+
+
+ENSEMBLE_GRIDS: Tuple[Tuple[int, int], ...] = ((4, 5), (4, 6), (5, 5))
+
+
+def make_ensemble(count: int, meta_seed: int = 3, grids: Sequence[Tuple[int, int]] = ENSEMBLE_GRIDS,
+                  depth_range: Tuple[int, int] = (20, 40), seed0: int = 3000) -> List[Circuit]:
+    """Ensemble of Sec. IV circuits of uneven size and depth: instance i has a
+    grid drawn uniformly from ``grids`` and a depth drawn uniformly from
+    ``depth_range`` (inclusive) by a SplitMix64 stream seeded with
+    ``meta_seed``, and circuit seed ``seed0 + i``."""
+    g = SplitMix64(meta_seed)
+    lo, hi = depth_range
+    out = []
+    for i in range(count):
+        r, c = grids[g.below(len(grids))]
+        d = lo + g.below(hi - lo + 1)
+        out.append(make_circuit(r, c, d, seed=seed0 + i))
+    return out

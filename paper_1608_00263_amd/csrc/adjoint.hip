@@ -179,8 +179,8 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
     cplx<T> phi[NR], mu[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-        phi[r] = uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r)))[lane];
-        mu[r] = uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r)))[lane];
+        phi[r] = gload<T>(uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r))) + lane);
+        mu[r] = gload<T>(uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r))) + lane);
     }
     const RTOp *ops = reinterpret_cast<const RTOp *>(prog + h->op_off);
     const DiagTerm *terms = reinterpret_cast<const DiagTerm *>(prog + h->term_off);
@@ -252,8 +252,8 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
     }
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-        uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r)))[lane] = phi[r];
-        uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r)))[lane] = mu[r];
+        gstore<T>(uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r))) + lane, phi[r]);
+        gstore<T>(uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r))) + lane, mu[r]);
     }
 }
 
@@ -323,7 +323,7 @@ static unsigned ggrid(uint64_t items) {
 
 template <typename T>
 static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *samples, int64_t k,
-                                double *loss, double *grad, int nparams) {
+                                double *loss, double *grad, int nparams, bool state_ready) {
     const int n = st->n;
     const uint64_t N = 1ull << n;
     hipStream_t s = st->stream;
@@ -353,8 +353,10 @@ static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *
     cplx<T> *phi = (cplx<T> *)st->data;
     auto ckpt = [&](int i) { return (cplx<T> *)(ck + (size_t)i * al(N * sizeof(cplx<T>))); };
 
-    // forward pass from |0..0>, storing checkpoints
+    // forward pass from |0..0>, storing checkpoints (skipped when the
+    // handle already holds the output state and no checkpoint is kept)
     for (const Op &op : plan.ops) {
+        if (state_ready) break;
         if (op.type == OP_CKPT_STORE) {
             SV_HIP(hipMemcpyAsync(ckpt(op.q0), phi, N * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
         } else {
@@ -420,6 +422,9 @@ extern "C" sv_status sv_backward(sv_state *st, const sv_circuit *c, const sv_opt
     if (k <= 0 || !samples || !loss || (c->nparams > 0 && !grad))
         return fail(SV_EINVAL, "need samples, a loss and a gradient buffer");
     if (checkpoint_c < 0) return fail(SV_EINVAL, "checkpoint interval must be >= 0");
+    const bool ready = opts && (opts->flags & SV_FLAG_STATE_READY);
+    if (ready && checkpoint_c != 0)
+        return fail(SV_EINVAL, "SV_FLAG_STATE_READY needs checkpoint_c = 0 (no forward pass to store them)");
     PlanRequest rq{};
     rq.n = st->n;
     rq.dtype = st->dt;
@@ -438,6 +443,6 @@ extern "C" sv_status sv_backward(sv_state *st, const sv_circuit *c, const sv_opt
         SV_TRY(upload_plan(st, plan.get()));
         st->plans[key] = plan;
     }
-    if (st->dt == SV_C64) return backward_typed<float>(st, *plan, samples, k, loss, grad, c->nparams);
-    return backward_typed<double>(st, *plan, samples, k, loss, grad, c->nparams);
+    if (st->dt == SV_C64) return backward_typed<float>(st, *plan, samples, k, loss, grad, c->nparams, ready);
+    return backward_typed<double>(st, *plan, samples, k, loss, grad, c->nparams, ready);
 }

@@ -45,8 +45,8 @@ constexpr int BLOCK = 256;
 
 // Value of the lane whose index differs in bit B (a wavefront has 64
 // lanes).  Bits 0..3 use DPP lane moves within rows of 16 (quad
-// permutations and row mirrors), bit 4 a ds_swizzle swap of 16-lane halves
-// of each 32, bit 5 a ds_bpermute.
+// permutations and row mirrors), bit 4 a ds_swizzle in xor mode (and mask
+// 0x1f, xor mask 16), bit 5 a ds_bpermute.
 template <int B>
 __device__ __forceinline__ int lane_xor_i(int v) {
     if constexpr (B == 0) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
@@ -59,7 +59,7 @@ __device__ __forceinline__ int lane_xor_i(int v) {
         int m = __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);
         return __builtin_amdgcn_mov_dpp(m, 0x141, 0xF, 0xF, false);
     }
-    if constexpr (B == 4) return __builtin_amdgcn_ds_swizzle(v, 0x401F);   // swap 16-lane halves
+    if constexpr (B == 4) return __builtin_amdgcn_ds_swizzle(v, 0x401F);   // lane ^ 16
     if constexpr (B == 5) return __shfl_xor(v, 32, 64);
     return v;
 }
@@ -242,15 +242,38 @@ __device__ __forceinline__ void lane_gate_dispatch(cplx<T> (&a)[NR], const Mat2<
     }
 }
 
+// Pointer into device (global) memory, address space 1: accesses through it
+// are global loads and stores rather than flat ones (no LDS-counter waits,
+// scalar base + 32-bit vector offset addressing).
+template <typename P> using gptr = __attribute__((address_space(1))) P *;
+
+// Pointer into device memory that no kernel writes while it runs (address
+// space 4): wave-uniform reads through it are scalar loads, also after the
+// kernel has stored to other buffers.
+template <typename P> using cptr = const __attribute__((address_space(4))) P *;
+
 // A wave-uniform pointer held in scalar registers, so that a wave-wide
 // access ptr[lane] uses the scalar-base + 32-bit lane-offset address form
-// (one address register per lane for all rows of a tile).
+// (one address register per lane for all rows of a tile).  p must point to
+// device memory.
 template <typename P>
-__device__ __forceinline__ P *uniform_ptr(P *p) {
+__device__ __forceinline__ gptr<P> uniform_ptr(P *p) {
     const uint64_t v = (uint64_t)p;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (P *)(((uint64_t)hi << 32) | lo);
+    return (gptr<P>)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> gload(gptr<cplx<T>> p) {
+    cplx<T> v;
+    v.re = p->re;
+    v.im = p->im;
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(gptr<cplx<T>> p, cplx<T> v) {
+    p->re = v.re;
+    p->im = v.im;
 }
 
 // Offset of register r in a register tile: sum of 2^rq[i] over the set
@@ -264,12 +287,104 @@ __device__ __forceinline__ uint64_t reg_offset(const uint64_t (&bq)[VB], int r) 
     return o;
 }
 
-template <typename T>
-__device__ __forceinline__ Mat2<T> load_mat(const double *u) {
+template <typename T, typename PD>
+__device__ __forceinline__ Mat2<T> load_mat(PD u) {
     Mat2<T> m;
 #pragma unroll
     for (int i = 0; i < 4; i++) { m.m[i].re = (T)u[2 * i]; m.m[i].im = (T)u[2 * i + 1]; }
     return m;
+}
+
+
+// One register tile of a sweep: tile index `tile` of the program at prog,
+// processed by the calling wavefront (lane = its lane id).
+template <typename T, int VB>
+__device__ __forceinline__ void regtile_apply(cplx<T> *__restrict__ psi, const uint8_t *__restrict__ prog,
+                                              uint64_t tile, int lane) {
+    constexpr int NR = 1 << VB;
+    const cptr<RTHeader> h = (cptr<RTHeader>)prog;
+    int rq[VB];
+#pragma unroll
+    for (int i = 0; i < VB; i++) rq[i] = h->rq[i];
+    uint64_t base = tile << LANE_BITS;
+#pragma unroll
+    for (int i = 0; i < VB; i++) base = insert_zero(base, rq[i]);
+    uint64_t bq[VB];
+#pragma unroll
+    for (int i = 0; i < VB; i++) bq[i] = 1ull << rq[i];
+
+    // uniform row pointer (scalar registers) + lane index: one address
+    // register per lane instead of one 64-bit address per amplitude
+    cplx<T> a[NR];
+    const int gen_n = h->gen_n;
+    if (gen_n > 0) {
+        // the Hadamard layer on |0..0>: every amplitude is 2^{-n/2}
+        T v = (T)ldexp(1.0, -(gen_n / 2));
+        if (gen_n & 1) v *= (T)0.70710678118654752440;
+#pragma unroll
+        for (int r = 0; r < NR; r++) { a[r].re = v; a[r].im = (T)0; }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) a[r] = gload<T>(uniform_ptr(psi + (base + reg_offset<VB>(bq, r))) + lane);
+    }
+
+    const cptr<RTOp> ops = (cptr<RTOp>)(prog + h->op_off);
+    const cptr<DiagTerm> terms = (cptr<DiagTerm>)(prog + h->term_off);
+    const int nops = h->nops;
+    for (int o = 0; o < nops; o++) {
+        const int kind = ops[o].kind;
+        const int arg = ops[o].a;
+        if (kind == RT_REG) {
+            reg_gate_dispatch<T, NR>(a, load_mat<T>(ops[o].u), arg, ops[o].form);
+        } else if (kind == RT_LANE) {
+            lane_gate_dispatch<T, NR>(a, load_mat<T>(ops[o].u), arg, lane, ops[o].form);
+        } else if (kind == RT_SIGNS) {
+            uint64_t par = 0;
+            const int nt = ops[o].nterms;
+            for (int t = arg; t < arg + nt; t++) {
+                const uint64_t out = terms[t].outside;
+                if ((base & out) != out) continue;
+                const uint32_t lm = terms[t].lanemask;
+                const uint64_t rs = terms[t].regset;
+                par ^= ((uint32_t)lane & lm) == lm ? rs : 0ull;
+            }
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                if ((par >> r) & 1) { a[r].re = -a[r].re; a[r].im = -a[r].im; }
+            }
+        } else if (kind == RT_PHASE) {
+            const uint64_t out = terms[arg].outside;
+            if ((base & out) == out) {
+                const uint32_t lm = terms[arg].lanemask;
+                const uint64_t rs = ((uint32_t)lane & lm) == lm ? terms[arg].regset : 0ull;
+                cplx<T> v;
+                v.re = (T)terms[arg].val[0];
+                v.im = (T)terms[arg].val[1];
+#pragma unroll
+                for (int r = 0; r < NR; r++)
+                    if ((rs >> r) & 1) a[r] = cmul(v, a[r]);
+            }
+        }
+    }
+    // the Clifford forms leave a power of sqrt2: 2^sexp exactly, then 1/sqrt2
+    const int sexp = h->sexp;
+    if (sexp != 0) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            a[r].re = ldexp(a[r].re, sexp);
+            a[r].im = ldexp(a[r].im, sexp);
+        }
+    }
+    if (h->shalf) {
+        const T rs = (T)0.70710678118654752440;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            a[r].re *= rs;
+            a[r].im *= rs;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) gstore<T>(uniform_ptr(psi + (base + reg_offset<VB>(bq, r))) + lane, a[r]);
 }
 
 

@@ -955,8 +955,13 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
                     if (!B->diag)
                         for (int q : B->qubits)
                             if (q >= LANE_BITS) tile.push_back(q);
-                // tiles of at least 2^12 (2^11 in complex128) amplitudes
-                int m = std::max(LANE_BITS + (int)tile.size(), std::min(rq.dtype == SV_C64 ? 12 : 11, rq.n));
+                // tiles of at least 2^12 (2^11 in complex128) amplitudes for
+                // blocks of 4 or more qubits (matrix-core fragments), 2^10 for
+                // narrower blocks (more workgroups in flight per CU)
+                int kw = 0;
+                for (const Block *B : grp) kw = std::max(kw, (int)B->qubits.size());
+                const int mmin = kw >= 4 ? (rq.dtype == SV_C64 ? 12 : 11) : 10;
+                int m = std::max(LANE_BITS + (int)tile.size(), std::min(mmin, rq.n));
                 m = std::min(m, rq.n);
                 emit_ldstile(g, grp, tile, m, rq.n, rq.dtype, plan, rq.no_mfma);
             }
@@ -1005,7 +1010,7 @@ sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int che
     }
     fold_diagonals(&g, rq.n, true);
     int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 4 : 3);
-    vb = std::max(1, std::min(vb, 4));
+    vb = std::max(1, std::min(vb, rq.dtype == SV_C64 ? 5 : 4));
     vb = std::min(vb, rq.n - LANE_BITS - 2);
     // segments of consecutive gates between checkpoints
     std::vector<std::vector<SGate>> segs(1);

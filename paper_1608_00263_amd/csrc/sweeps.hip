@@ -117,94 +117,11 @@ template <typename T, int VB>
 __global__ __launch_bounds__(BLOCK) void k_regtile(cplx<T> *__restrict__ psi,
                                                    const uint8_t *__restrict__ prog,
                                                    uint64_t ntiles) {
-    constexpr int NR = 1 << VB;
-    const RTHeader *h = reinterpret_cast<const RTHeader *>(prog);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t tile = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
     if (tile >= ntiles) return;
-    int rq[VB];
-#pragma unroll
-    for (int i = 0; i < VB; i++) rq[i] = h->rq[i];
-    uint64_t base = tile << LANE_BITS;
-#pragma unroll
-    for (int i = 0; i < VB; i++) base = insert_zero(base, rq[i]);
-    uint64_t bq[VB];
-#pragma unroll
-    for (int i = 0; i < VB; i++) bq[i] = 1ull << rq[i];
-
-    // uniform row pointer (scalar registers) + lane index: one address
-    // register per lane instead of one 64-bit address per amplitude
-    cplx<T> a[NR];
-    const int gen_n = h->gen_n;
-    if (gen_n > 0) {
-        // the Hadamard layer on |0..0>: every amplitude is 2^{-n/2}
-        T v = (T)ldexp(1.0, -(gen_n / 2));
-        if (gen_n & 1) v *= (T)0.70710678118654752440;
-#pragma unroll
-        for (int r = 0; r < NR; r++) { a[r].re = v; a[r].im = (T)0; }
-    } else {
-#pragma unroll
-        for (int r = 0; r < NR; r++) a[r] = uniform_ptr(psi + (base + reg_offset<VB>(bq, r)))[lane];
-    }
-
-    const RTOp *ops = reinterpret_cast<const RTOp *>(prog + h->op_off);
-    const DiagTerm *terms = reinterpret_cast<const DiagTerm *>(prog + h->term_off);
-    const int nops = h->nops;
-    for (int o = 0; o < nops; o++) {
-        const int kind = ops[o].kind;
-        const int arg = ops[o].a;
-        if (kind == RT_REG) {
-            reg_gate_dispatch<T, NR>(a, load_mat<T>(ops[o].u), arg, ops[o].form);
-        } else if (kind == RT_LANE) {
-            lane_gate_dispatch<T, NR>(a, load_mat<T>(ops[o].u), arg, lane, ops[o].form);
-        } else if (kind == RT_SIGNS) {
-            uint64_t par = 0;
-            const int nt = ops[o].nterms;
-            for (int t = arg; t < arg + nt; t++) {
-                const uint64_t out = terms[t].outside;
-                if ((base & out) != out) continue;
-                const uint32_t lm = terms[t].lanemask;
-                const uint64_t rs = terms[t].regset;
-                par ^= ((uint32_t)lane & lm) == lm ? rs : 0ull;
-            }
-#pragma unroll
-            for (int r = 0; r < NR; r++) {
-                if ((par >> r) & 1) { a[r].re = -a[r].re; a[r].im = -a[r].im; }
-            }
-        } else if (kind == RT_PHASE) {
-            const uint64_t out = terms[arg].outside;
-            if ((base & out) == out) {
-                const uint32_t lm = terms[arg].lanemask;
-                const uint64_t rs = ((uint32_t)lane & lm) == lm ? terms[arg].regset : 0ull;
-                cplx<T> v;
-                v.re = (T)terms[arg].val[0];
-                v.im = (T)terms[arg].val[1];
-#pragma unroll
-                for (int r = 0; r < NR; r++)
-                    if ((rs >> r) & 1) a[r] = cmul(v, a[r]);
-            }
-        }
-    }
-    // the Clifford forms leave a power of sqrt2: 2^sexp exactly, then 1/sqrt2
-    const int sexp = h->sexp;
-    if (sexp != 0) {
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-            a[r].re = ldexp(a[r].re, sexp);
-            a[r].im = ldexp(a[r].im, sexp);
-        }
-    }
-    if (h->shalf) {
-        const T rs = (T)0.70710678118654752440;
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-            a[r].re *= rs;
-            a[r].im *= rs;
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < NR; r++) uniform_ptr(psi + (base + reg_offset<VB>(bq, r)))[lane] = a[r];
+    regtile_apply<T, VB>(psi, prog, tile, lane);
 }
 
 // ---------------------------------------------------------------------------

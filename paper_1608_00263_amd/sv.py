@@ -148,11 +148,14 @@ class CircuitArgs:
 
 FLAG_FROM_ZERO = 1
 FLAG_NO_MFMA = 2
+FLAG_STATE_READY = 4
+FLAG_BATCH_LAUNCHES = 8
+FLAG_BATCH_PERSISTENT = 16
 
 
-def make_opts(mode="auto", k_max=0, tile=0, from_zero=False, no_mfma=False) -> Opts:
+def make_opts(mode="auto", k_max=0, tile=0, from_zero=False, no_mfma=False, flags=0) -> Opts:
     m = MODES[mode] if isinstance(mode, str) else int(mode)
-    return Opts(m, k_max, tile, (FLAG_FROM_ZERO if from_zero else 0) | (FLAG_NO_MFMA if no_mfma else 0))
+    return Opts(m, k_max, tile, (FLAG_FROM_ZERO if from_zero else 0) | (FLAG_NO_MFMA if no_mfma else 0) | flags)
 
 
 def _stream_handle(torch):
@@ -262,9 +265,12 @@ class State:
         return ce.value, dh.value, z.value
 
     def backward(self, circ, samples: np.ndarray, checkpoint_c: int = 0, mode="auto", k_max=0,
-                 tile=0):
+                 tile=0, state_ready=False):
+        """Loss and adjoint gradient; state_ready=True reuses the output state
+        the handle holds (left by apply() of the same circuit) instead of
+        recomputing it."""
         a = CircuitArgs(circ)
-        o = make_opts(mode, k_max, tile)
+        o = make_opts(mode, k_max, tile, flags=FLAG_STATE_READY if state_ready else 0)
         x = np.ascontiguousarray(samples, dtype=np.uint64)
         grad = np.zeros(max(circ.nparams, 1))
         loss = ctypes.c_double()
@@ -284,14 +290,26 @@ def sample_from(probs, words, torch=None):
     return out[:words.numel()]
 
 
-def apply_batch(states, circuits, mode="auto", k_max=0, tile=0):
-    """Simulate each circuit from |0..0> into its state; returns per-instance stats."""
-    args = [CircuitArgs(c) for c in circuits]
-    arr = (CCircuit * len(args))(*[a.c for a in args])
+class BatchArgs:
+    """Marshalled circuits of an ensemble (reusable across calls)."""
+
+    def __init__(self, circuits):
+        self.args = [CircuitArgs(c) for c in circuits]
+        self.arr = (CCircuit * len(self.args))(*[a.c for a in self.args])
+
+
+def apply_batch(states, circuits, mode="auto", k_max=0, tile=0, launches=False,
+                persistent=False, args: Optional[BatchArgs] = None):
+    """Simulate each circuit from |0..0> into its state; returns per-instance
+    stats.  Default schedule: one launch per sweep round over all instances;
+    persistent=True: one persistent launch with a work queue; launches=True:
+    the ordinary per-instance launches."""
+    ba = args or BatchArgs(circuits)      # keeps the gate arrays alive during the call
     hs = (ctypes.c_void_p * len(states))(*[s.h.value for s in states])
     out = (Stats * len(states))()
-    o = make_opts(mode, k_max, tile)
-    check(lib().sv_apply_batch(hs, arr, len(states), ctypes.byref(o), out))
+    o = make_opts(mode, k_max, tile, flags=(FLAG_BATCH_LAUNCHES if launches else 0)
+                  | (FLAG_BATCH_PERSISTENT if persistent else 0))
+    check(lib().sv_apply_batch(hs, ba.arr, len(states), ctypes.byref(o), out))
     return [s.as_dict() for s in out]
 
 

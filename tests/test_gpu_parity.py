@@ -223,3 +223,120 @@ def test_batch_matches_oracle():
         np.testing.assert_allclose(r["moments"][:5], want["moments"][:5], rtol=1e-3)
         assert np.linalg.norm(st.amplitudes() - ref) < 1e-4
         st.close()
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("tile", [0, 3, 4, 5])
+def test_batch_tables_uneven_sizes(tile, persistent):
+    # instances of 14..18 qubits and depths 7..20: sweeps of different
+    # instances interleave in the persistent queue
+    shapes = [(2, 7, 14), (3, 5, 18), (4, 4, 11), (2, 8, 20), (3, 6, 7), (2, 7, 3)]
+    circs = [C.make_circuit(r, c, d, seed=400 + i) for i, (r, c, d) in enumerate(shapes)]
+    states = [sv.State(c.n, "c64") for c in circs]
+    res = sv.apply_batch(states, circs, mode="regtile" if tile else "auto", tile=tile, persistent=persistent)
+    for c, st, r in zip(circs, states, res):
+        ref = oracle.apply_circuit(c)
+        assert np.linalg.norm(st.amplitudes() - ref) <= TOL["c64"]
+        want = oracle.stats(oracle.probs(ref))
+        assert abs(r["entropy"] - want["entropy"]) < 1e-4
+        assert abs(r["unif_ce"] - want["unif_ce"]) < 1e-4
+        assert abs(r["norm"] - 1.0) < 1e-5 and r["zero_count"] == want["zero_count"]
+        np.testing.assert_allclose(r["moments"][:5], want["moments"][:5], rtol=1e-3)
+        # the ensemble's statistics equal those of the single-state pass on
+        # the same amplitudes up to the summation order
+        m = st.moments()
+        assert abs(m["entropy"] - r["entropy"]) < 1e-10
+        np.testing.assert_allclose(r["moments"], m["moments"], rtol=1e-10)
+    for st in states:
+        st.close()
+
+
+def test_batch_schedules_agree_and_repeat():
+    circs = [C.make_circuit(3, 5, 16, seed=500 + i) for i in range(5)]
+    a = [sv.State(c.n, "c64") for c in circs]
+    b = [sv.State(c.n, "c64") for c in circs]
+    p = [sv.State(c.n, "c64") for c in circs]
+    r1 = sv.apply_batch(a, circs)
+    r2 = sv.apply_batch(b, circs, launches=True)
+    r3 = sv.apply_batch(a, circs)          # graph replayed over its own output
+    r4 = sv.apply_batch(p, circs, persistent=True)
+    r5 = sv.apply_batch(p, circs, persistent=True)
+    for x, y, z, u, w, sa, sb, sp in zip(r1, r2, r3, r4, r5, a, b, p):
+        assert abs(x["entropy"] - y["entropy"]) < 1e-6
+        assert x["entropy"] == z["entropy"] and (x["moments"] == z["moments"]).all()
+        # same tiles, same partial rows: the two table schedules agree exactly
+        assert x["entropy"] == u["entropy"] == w["entropy"] and (x["moments"] == u["moments"]).all()
+        assert np.linalg.norm(sa.amplitudes() - sb.amplitudes()) < 1e-5
+        assert np.array_equal(sa.amplitudes(), sp.amplitudes())
+    for st in a + b + p:
+        st.close()
+
+
+def test_batch_c128_and_empty():
+    circs = [C.make_circuit(2, 7, 10, seed=600 + i) for i in range(3)]
+    states = [sv.State(c.n, "c128") for c in circs]
+    res = sv.apply_batch(states, circs)
+    for c, st, r in zip(circs, states, res):
+        ref = oracle.apply_circuit(c)
+        assert np.linalg.norm(st.amplitudes() - ref) <= TOL["c128"]
+        want = oracle.stats(oracle.probs(ref))
+        assert abs(r["entropy"] - want["entropy"]) < 1e-10
+        st.close()
+    assert sv.apply_batch([], []) == []
+
+
+# ---------------------------------------------------------------------------
+# adjoint through torch.autograd
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ck", [0, 3])
+def test_autograd_cross_entropy(ck):
+    from paper_1608_00263_amd.autograd import CircuitCrossEntropy
+    circ = C.make_circuit(3, 4, 14, seed=71, parametrise=True, theta_seed=72, theta_std=0.05)
+    p0 = oracle.probs(oracle.apply_circuit(circ.with_theta(np.zeros(circ.nparams))))
+    xs = oracle.sample(p0, 3000, 1005)
+    loss0, g0 = oracle.adjoint(circ, xs)
+    f = CircuitCrossEntropy(circ, xs, dtype="c128", checkpoint_c=ck)
+    theta = torch.tensor(circ.theta, dtype=torch.float64, requires_grad=True)
+    loss = f(theta)
+    loss.backward()
+    assert abs(loss.item() - loss0) < 1e-9
+    np.testing.assert_allclose(theta.grad.numpy(), g0, atol=1e-9)
+    # a second step at other parameters reuses the module's state
+    theta2 = torch.tensor(circ.theta * 0.5, dtype=torch.float64, requires_grad=True)
+    l2 = f(theta2)
+    (3.0 * l2).backward()
+    loss1, g1 = oracle.adjoint(circ.with_theta(circ.theta * 0.5), xs)
+    assert abs(l2.item() - loss1) < 1e-9
+    np.testing.assert_allclose(theta2.grad.numpy(), 3.0 * g1, atol=1e-9)
+    f.close()
+
+
+def test_backward_state_ready_matches_full():
+    circ = C.make_circuit(4, 4, 20, seed=81, parametrise=True, theta_seed=82, theta_std=0.05)
+    p0 = oracle.probs(oracle.apply_circuit(circ.with_theta(np.zeros(circ.nparams))))
+    xs = oracle.sample(p0, 5000, 1006)
+    st = sv.State(circ.n, "c64")
+    loss_a, g_a = st.backward(circ, xs)
+    st.apply(circ, "auto", from_zero=True)
+    loss_b, g_b = st.backward(circ, xs, state_ready=True)
+    assert abs(loss_a - loss_b) < 1e-5
+    np.testing.assert_allclose(g_b, g_a, atol=2e-5)
+    with pytest.raises(sv.SVError) as e:
+        st.backward(circ, xs, checkpoint_c=2, state_ready=True)
+    assert e.value.status == sv.SV_EINVAL
+    st.close()
+
+
+def test_ensemble_recipe_small():
+    # the ensemble recipe of the benchmark at sizes the reference finishes
+    # quickly: every instance against the reference, all in one persistent launch
+    circs = C.make_ensemble(12, meta_seed=5, grids=((2, 7), (3, 5), (4, 4)), depth_range=(8, 20),
+                            seed0=700)
+    states = [sv.State(c.n, "c64") for c in circs]
+    res = sv.apply_batch(states, circs)
+    for c, st, r in zip(circs, states, res):
+        ref = oracle.apply_circuit(c)
+        assert np.linalg.norm(st.amplitudes() - ref) <= TOL["c64"]
+        want = oracle.stats(oracle.probs(ref))
+        assert abs(r["entropy"] - want["entropy"]) < 1e-4
+        st.close()
