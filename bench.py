@@ -43,13 +43,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="regtile")
-    ap.add_argument("--tile", type=int, default=5)
+    ap.add_argument("--tile", type=int, default=6)
     ap.add_argument("--samples", type=int, default=100000)
     ap.add_argument("--no-modes", action="store_true", help="skip the per-mode circuit timings")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the ensemble timing")
     ap.add_argument("--ensemble", type=int, default=512, help="ensemble instances")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed steps, copy an 8 GiB buffer three times (a plain copy "
+                         "kernel of known size, the calibration of the HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -160,6 +163,8 @@ def main():
         "results": {"entropy": mom["entropy"], "unif_ce": mom["unif_ce"], "norm": mom["norm"],
                     "M2": mom["M2"], "M10": mom["M10"], "ce": ce, "delta_h": dh},
     }
+    if a.copy_probe:
+        out["copy_probe"] = copy_probe(torch)
     if not a.no_modes:
         out["circuit_s"] = mode_timings(sv, C, circ, torch)
     if not a.no_grad:
@@ -173,6 +178,22 @@ def main():
         log("cpu baseline (%.0f s budget)" % a.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(circ, a.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def copy_probe(torch):
+    """torch's device copy of 2^30 complex64 (8 GiB read + 8 GiB write), three times."""
+    x = torch.empty(1 << 30, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    del x, y
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * 8.0 * 2 ** 30, "s": round(dt, 5), "GBps": round(2 * 8.0 * 2 ** 30 / dt / 1e9, 1)}
 
 
 def mode_timings(sv, C, circ, torch):

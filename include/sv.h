@@ -119,6 +119,10 @@ typedef struct {
     int32_t tile_qubits;  /* TILED: 8..13 (0 = default); REGTILE: register
                              qubits 1..6 (0 = default)                        */
     int32_t flags;        /* SV_FLAG_* bits                                   */
+    int32_t sweep_budget; /* REGTILE: vector instructions per amplitude
+                             register one sweep may spend on gates before a
+                             new sweep starts (0 = default, 110 complex64,
+                             220 complex128; 20..2000)                       */
 } sv_opts;
 
 /* Output statistics of p_hat = p / S (Secs. II and IV):

@@ -29,6 +29,11 @@ def _flags():
             # keep the per-case register-tile code separate: merging the switch
             # cases makes the amplitude registers addressable (scratch spills)
             "-mllvm", "-simplifycfg-sink-common=false",
+            # leave regions under wave-uniform branches unstructured: the op
+            # dispatch of the tile programs branches on scalar values only,
+            # and structuring it merges the amplitude registers through
+            # flow blocks (register copies at every op)
+            "-mllvm", "-structurizecfg-skip-uniform-regions=true",
             "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"),
             "-D__HIP_PLATFORM_AMD__"]
 

@@ -73,6 +73,7 @@ static PlanRequest make_request(sv_state *st, const sv_opts *o) {
     rq.mode = o ? o->mode : SV_MODE_AUTO;
     rq.k_max = o ? o->k_max : 0;
     rq.tile = o ? o->tile_qubits : 0;
+    rq.budget = o ? o->sweep_budget : 0;
     rq.force_zero = o && (o->flags & SV_FLAG_FROM_ZERO);
     rq.from_zero = st->known_zero || rq.force_zero;
     rq.no_mfma = o && (o->flags & SV_FLAG_NO_MFMA);
@@ -86,7 +87,7 @@ static std::map<std::string, sv_opts> g_tuned;   // process-wide choices
 
 static std::vector<sv_opts> tune_candidates(const sv_state *st) {
     std::vector<sv_opts> c;
-    auto add = [&](int mode, int k, int t) { c.push_back(sv_opts{mode, k, t, 0}); };
+    auto add = [&](int mode, int k, int t) { c.push_back(sv_opts{mode, k, t, 0, 0}); };
     if (st->n >= 10) {
         if (st->dt == SV_C64) { add(SV_MODE_REGTILE, 0, 4); add(SV_MODE_REGTILE, 0, 5); add(SV_MODE_REGTILE, 0, 6); }
         else { add(SV_MODE_REGTILE, 0, 3); add(SV_MODE_REGTILE, 0, 4); }
@@ -199,6 +200,7 @@ sv_status get_plan(sv_state *st, const sv_circuit *c, PlanRequest rq, std::share
     if (rq.mode == SV_MODE_AUTO) rq.mode = SV_MODE_REGTILE;   // only without a handle-level choice
     if (rq.mode < SV_MODE_PLAIN || rq.mode > SV_MODE_REGTILE) return fail(SV_EINVAL, "unknown mode");
     if (rq.k_max < 0 || rq.k_max > 5) return fail(SV_EINVAL, "k_max must be 0..5");
+    if (rq.budget != 0 && (rq.budget < 20 || rq.budget > 2000)) return fail(SV_EINVAL, "sweep_budget must be 0 or 20..2000");
     std::string key = plan_key(c, rq);
     auto it = st->plans.find(key);
     if (it != st->plans.end()) {

@@ -154,10 +154,63 @@ __device__ __forceinline__ void reg_gate_dispatch(cplx<T> (&a)[NR], const Mat2<T
     }
 }
 
+// Lane bits 4 and 5 through the gfx950 half-swaps of two registers x, y:
+// permlane32_swap exchanges the upper 32 lanes of x with the lower 32 of y,
+// permlane16_swap the odd 16-lane rows of x with the even rows of y.  After
+// the swap every lane holds one partner pair (bit B clear in x, set in y):
+// lanes with bit B clear hold the pair of the first register, the others
+// that of the second.  The same swap restores the layout.
+template <int B>
+__device__ __forceinline__ void half_swap_i(int &x, int &y) {
+    static_assert(B == 4 || B == 5, "half swaps exist for lane bits 4 and 5");
+    if constexpr (B == 5) {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+        x = (int)r[0];
+        y = (int)r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+        x = (int)r[0];
+        y = (int)r[1];
+    }
+}
+template <int B>
+__device__ __forceinline__ void half_swap(float &x, float &y) {
+    int xi = __float_as_int(x), yi = __float_as_int(y);
+    half_swap_i<B>(xi, yi);
+    x = __int_as_float(xi);
+    y = __int_as_float(yi);
+}
+template <int B>
+__device__ __forceinline__ void half_swap(double &x, double &y) {
+    const long long xb = __double_as_longlong(x), yb = __double_as_longlong(y);
+    int xl = (int)(xb & 0xffffffffll), xh = (int)(xb >> 32);
+    int yl = (int)(yb & 0xffffffffll), yh = (int)(yb >> 32);
+    half_swap_i<B>(xl, yl);
+    half_swap_i<B>(xh, yh);
+    x = __longlong_as_double(((long long)xh << 32) | (unsigned int)xl);
+    y = __longlong_as_double(((long long)yh << 32) | (unsigned int)yl);
+}
+
 // Gate on lane bit B: each lane forms its new value from its own amplitude
-// (self) and its partner's (p); hi = the lane's bit B.
+// (self) and its partner's (p); hi = the lane's bit B.  Bits 4 and 5 swap
+// register halves instead so that each lane applies the gate to a whole
+// pair (no lane-dependent coefficients).
 template <typename T, int NR, int B, int FORM>
 __device__ __forceinline__ void lane_gate_f(cplx<T> (&a)[NR], const Mat2<T> &u, int lane) {
+    if constexpr (B >= 4 && FORM != F_PHASE && NR >= 2) {
+#pragma unroll
+        for (int r = 0; r < NR; r += 2) {
+            cplx<T> x = a[r], y = a[r + 1];
+            half_swap<B>(x.re, y.re);
+            half_swap<B>(x.im, y.im);
+            pair_form<T, FORM>(x, y, u);
+            half_swap<B>(x.re, y.re);
+            half_swap<B>(x.im, y.im);
+            a[r] = x;
+            a[r + 1] = y;
+        }
+        return;
+    }
     const bool hi = (lane >> B) & 1;
     if constexpr (FORM == F_PHASE) {
         cplx<T> f;

@@ -242,6 +242,8 @@ static sv_status host_plan(const sv_circuit *c, sv_dtype dt, const sv_opts *o, i
     if (rq.mode == SV_MODE_AUTO) rq.mode = SV_MODE_REGTILE;
     rq.k_max = o ? o->k_max : 0;
     rq.tile = o ? o->tile_qubits : 0;
+    rq.budget = o ? o->sweep_budget : 0;
+    if (rq.budget != 0 && (rq.budget < 20 || rq.budget > 2000)) return fail(SV_EINVAL, "sweep_budget must be 0 or 20..2000");
     rq.from_zero = from_zero != 0;
     rq.force_zero = o && (o->flags & SV_FLAG_FROM_ZERO);
     return build_plan(c, rq, plan);
@@ -287,7 +289,9 @@ extern "C" sv_status sv_host_plan_describe(const sv_circuit *c, sv_dtype dt, con
             const RTHeader *h = (const RTHeader *)(plan.prog.data() + op.prog_off);
             const RTOp *ops = (const RTOp *)((const uint8_t *)h + h->op_off);
             int nreg = 0, nlane = 0, nsign = 0, nterm = 0, nphase = 0;
+            int nform[10] = {0};
             for (int o = 0; o < h->nops; o++) {
+                if (ops[o].kind == RT_REG || ops[o].kind == RT_LANE) nform[std::min(9, std::max(0, (int)ops[o].form))]++;
                 if (ops[o].kind == RT_REG) nreg++;
                 else if (ops[o].kind == RT_LANE) nlane++;
                 else if (ops[o].kind == RT_SIGNS) { nsign++; nterm += ops[o].nterms; }
@@ -295,8 +299,12 @@ extern "C" sv_status sv_host_plan_describe(const sv_circuit *c, sv_dtype dt, con
             }
             std::string rq;
             for (int j = 0; j < h->vbits; j++) rq += (j ? "," : "") + std::to_string(h->rq[j]);
-            snprintf(line, sizeof line, "%zu regtile v=%d rq=[%s] reg=%d lane=%d signops=%d cz=%d phase=%d\n", i,
-                     h->vbits, rq.c_str(), nreg, nlane, nsign, nterm, nphase);
+            std::string fs;
+            static const char *fname[10] = {"gen", "h", "sx", "sy", "sxdg", "sydg", "phase", "rx", "ry", "real"};
+            for (int f = 0; f < 10; f++)
+                if (nform[f]) fs += std::string(fs.empty() ? "" : ",") + fname[f] + ":" + std::to_string(nform[f]);
+            snprintf(line, sizeof line, "%zu regtile v=%d rq=[%s] reg=%d lane=%d signops=%d cz=%d phase=%d forms=[%s]\n",
+                     i, h->vbits, rq.c_str(), nreg, nlane, nsign, nterm, nphase, fs.c_str());
         } else if (op.type == OP_LDSTILE) {
             const LTHeader *h = (const LTHeader *)(plan.prog.data() + op.prog_off);
             const LTOp *ops = (const LTOp *)((const uint8_t *)h + h->op_off);

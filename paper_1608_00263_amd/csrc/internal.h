@@ -227,6 +227,7 @@ struct PlanRequest {
     int mode;
     int k_max;
     int tile;            // tile qubits (TILED) / register qubits (REGTILE)
+    int budget;          // REGTILE arithmetic budget per sweep (0 = default)
     bool from_zero;      // state is |0..0>: a leading Hadamard layer may be
                          // replaced by the uniform initialisation
     bool force_zero;     // the plan must itself start from |0..0>

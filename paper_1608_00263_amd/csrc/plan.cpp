@@ -918,7 +918,7 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
         int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 5 : 4);
         vb = std::max(1, std::min(vb, rq.dtype == SV_C64 ? 6 : 5));
         vb = std::min(vb, rq.n - LANE_BITS);
-        auto sweeps = regtile_sweeps(g, rq.n, vb, rq.dtype);
+        auto sweeps = regtile_sweeps(g, rq.n, vb, rq.dtype, rq.budget > 0 ? (double)rq.budget : -1.0);
         std::vector<std::pair<size_t, int>> scales;
         for (const Sweep &sw : sweeps) emit_regtile(g, sw, vb, rq.n, rq.dtype, plan, &scales);
         assign_scales(plan, scales);

@@ -43,7 +43,8 @@ class CCircuit(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("k_max", ctypes.c_int32),
-                ("tile_qubits", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("tile_qubits", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("sweep_budget", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -153,9 +154,10 @@ FLAG_BATCH_LAUNCHES = 8
 FLAG_BATCH_PERSISTENT = 16
 
 
-def make_opts(mode="auto", k_max=0, tile=0, from_zero=False, no_mfma=False, flags=0) -> Opts:
+def make_opts(mode="auto", k_max=0, tile=0, from_zero=False, no_mfma=False, flags=0, budget=0) -> Opts:
     m = MODES[mode] if isinstance(mode, str) else int(mode)
-    return Opts(m, k_max, tile, (FLAG_FROM_ZERO if from_zero else 0) | (FLAG_NO_MFMA if no_mfma else 0) | flags)
+    return Opts(m, k_max, tile, (FLAG_FROM_ZERO if from_zero else 0) | (FLAG_NO_MFMA if no_mfma else 0) | flags,
+                budget)
 
 
 def _stream_handle(torch):
@@ -195,17 +197,17 @@ class State:
         check(lib().sv_reset(self.h))
 
     def apply(self, circ, mode="auto", k_max=0, tile=0, args: Optional[CircuitArgs] = None,
-              from_zero=False, no_mfma=False):
+              from_zero=False, no_mfma=False, budget=0):
         """Apply circ in place (from |0..0> regardless of contents if from_zero)."""
         a = args or CircuitArgs(circ)
-        o = make_opts(mode, k_max, tile, from_zero, no_mfma)
+        o = make_opts(mode, k_max, tile, from_zero, no_mfma, budget=budget)
         check(lib().sv_apply_circuit(self.h, a.ref, ctypes.byref(o)))
 
     def apply_timed(self, circ, mode="auto", k_max=0, tile=0, args: Optional[CircuitArgs] = None,
-                    from_zero=False):
+                    from_zero=False, budget=0):
         """Apply with per-sweep HIP event timing; returns (ms, kinds, bytes) arrays."""
         a = args or CircuitArgs(circ)
-        o = make_opts(mode, k_max, tile, from_zero)
+        o = make_opts(mode, k_max, tile, from_zero, budget=budget)
         cap = 4096
         ms = np.zeros(cap, dtype=np.float32)
         kinds = np.zeros(cap, dtype=np.int32)
@@ -223,11 +225,11 @@ class State:
         done = ctypes.c_int()
         check(lib().sv_autotune(self.h, a.ref, 1 if from_zero else 0, ctypes.byref(o), ctypes.byref(done)))
         name = {v: k for k, v in MODES.items()}[o.mode]
-        return name, o.k_max, o.tile_qubits, bool(done.value)
+        return name, o.k_max, o.tile_qubits, bool(done.value), o.sweep_budget
 
-    def plan_info(self, circ, mode="auto", k_max=0, tile=0, no_mfma=False):
+    def plan_info(self, circ, mode="auto", k_max=0, tile=0, no_mfma=False, budget=0):
         a = CircuitArgs(circ)
-        o = make_opts(mode, k_max, tile, no_mfma=no_mfma)
+        o = make_opts(mode, k_max, tile, no_mfma=no_mfma, budget=budget)
         sw = ctypes.c_int64()
         by = ctypes.c_double()
         check(lib().sv_plan_info(self.h, a.ref, ctypes.byref(o), ctypes.byref(sw), ctypes.byref(by)))
@@ -314,9 +316,9 @@ def apply_batch(states, circuits, mode="auto", k_max=0, tile=0, launches=False,
 
 
 # ---- host-only diagnostics (no GPU) -----------------------------------------
-def host_plan(circ, dtype="c64", mode="auto", k_max=0, tile=0, from_zero=True):
+def host_plan(circ, dtype="c64", mode="auto", k_max=0, tile=0, from_zero=True, budget=0):
     a = CircuitArgs(circ)
-    o = make_opts(mode, k_max, tile)
+    o = make_opts(mode, k_max, tile, budget=budget)
     sw = ctypes.c_int64()
     by = ctypes.c_double()
     mf = ctypes.c_int64()
@@ -327,18 +329,19 @@ def host_plan(circ, dtype="c64", mode="auto", k_max=0, tile=0, from_zero=True):
 
 
 def host_emulate(circ, psi: np.ndarray, dtype="c64", mode="auto", k_max=0, tile=0,
-                 from_zero=True) -> np.ndarray:
+                 from_zero=True, budget=0) -> np.ndarray:
     a = CircuitArgs(circ)
-    o = make_opts(mode, k_max, tile)
+    o = make_opts(mode, k_max, tile, budget=budget)
     psi = np.ascontiguousarray(psi, dtype=np.complex128).copy()
     check(lib().sv_host_emulate(a.ref, C64 if dtype == "c64" else C128, ctypes.byref(o),
                                 1 if from_zero else 0, _ptr(psi)))
     return psi
 
 
-def host_plan_describe(circ, dtype="c64", mode="auto", k_max=0, tile=0, from_zero=True) -> str:
+def host_plan_describe(circ, dtype="c64", mode="auto", k_max=0, tile=0, from_zero=True,
+                       budget=0) -> str:
     a = CircuitArgs(circ)
-    o = make_opts(mode, k_max, tile)
+    o = make_opts(mode, k_max, tile, budget=budget)
     buf = ctypes.create_string_buffer(1 << 20)
     check(lib().sv_host_plan_describe(a.ref, C64 if dtype == "c64" else C128, ctypes.byref(o),
                                       1 if from_zero else 0, buf, len(buf)))
