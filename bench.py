@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the ensemble timing")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 35-qubit run")
     ap.add_argument("--ensemble", type=int, default=512, help="ensemble instances")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, copy an 8 GiB buffer three times (a plain copy "
@@ -171,6 +172,8 @@ def main():
         out["grad"] = grad_timings(sv, C, torch)
     if not a.no_ensemble:
         out["ensemble"] = ensemble_timings(sv, C, torch, a.ensemble)
+    if not a.no_c5:
+        out["c5"] = c5_run(sv, C, torch)
     st.close()
     del st
     torch.cuda.empty_cache()
@@ -234,6 +237,52 @@ def mode_timings(sv, C, circ, torch):
     return res
 
 
+def c5_run(sv, C, torch):
+    """The 5x7 grid, 35 qubits, depth 40, complex64 in place (256 GiB):
+    register-tile sweeps timed per launch, statistics, 10^6 samples and
+    their cross entropy."""
+    import numpy as np
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info(0)
+    if free < 8 * 2 ** 35 + (4 << 30):
+        return {"skipped": "needs 260 GiB of free device memory, %.0f GiB free" % (free / 2 ** 30)}
+    circ = C.make_circuit(5, 7, 40, seed=5)
+    args = sv.CircuitArgs(circ)
+    st = sv.State(35, "c64")
+    S = 8.0 * 2 ** 35
+    out = {"workload": "5x7 grid, 35 qubits, depth 40 (%d gates), complex64 in place, 1e6 samples"
+                       % circ.ngates}
+    runs = []
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms, kinds, by = st.apply_timed(circ, "regtile", 0, 6, args=args, from_zero=True)
+        torch.cuda.synchronize()
+        runs.append((time.perf_counter() - t0, ms, by))
+        log("c5 circuit: %.3f s, %d sweeps" % (runs[-1][0], len(ms)))
+    dt, ms, by = runs[-1]
+    t0 = time.perf_counter()
+    m = st.moments()
+    t_stats = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    xs = st.sample(10 ** 6, 1005)
+    t_sample = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ce, dh, z = st.cross_entropy(xs)
+    t_ce = time.perf_counter() - t0
+    gbps = float(by.sum()) / (float(ms.sum()) / 1e3) / 1e9
+    out.update({"circuit_s": round(dt, 4), "sweeps": len(ms), "sweep_ms_avg": round(float(ms.mean()), 3),
+                "sweep_GBps": round(gbps, 1), "sweep_frac_of_peak": round(gbps / PEAK_HBM_GBPS, 4),
+                "stats_s": round(t_stats, 4), "sample_s": round(t_sample, 4), "ce_s": round(t_ce, 4),
+                "norm": m["norm"], "entropy": m["entropy"],
+                "entropy_porter_thomas": 35 * math.log(2.0) - 1.0 + 0.5772156649015329,
+                "M2": m["M2"], "M3": m["M3"], "ce": ce, "delta_h": dh, "zero_samples": z})
+    st.close()
+    del st
+    torch.cuda.empty_cache()
+    return out
+
+
 def ensemble_timings(sv, C, torch, count, reps=3):
     """The ensemble of Sec. IV circuits (grids 4x5, 4x6, 5x5; depth 20..40):
     one launch per sweep round over all instances (default), the persistent
@@ -278,30 +327,47 @@ def ensemble_timings(sv, C, torch, count, reps=3):
 
 
 def grad_timings(sv, C, torch):
+    """Adjoint gradient of the 5x5 depth-30 parametrised circuit (every
+    non-Hadamard gate a rotation offset, theta ~ N(0, 0.05^2)) on 10^4
+    samples of the theta = 0 circuit: backward seconds over forward seconds.
+    ready_cN: the backward reuses the output state of the forward (what an
+    autograd step does); full_cN: the backward recomputes the forward and
+    keeps a state copy every N cycles."""
     import numpy as np
     circ = C.make_circuit(5, 5, 30, seed=4, parametrise=True, theta_seed=4004, theta_std=0.05)
     nominal = circ.with_theta(np.zeros(circ.nparams))
     st = sv.State(circ.n, "c64")
-    st.apply(nominal, "regtile", 0, 5, from_zero=True)
+    st.apply(nominal, "regtile", 0, 6, from_zero=True)
     xs = st.sample(10000, 1004)
     args = sv.CircuitArgs(circ)
-    st.apply(circ, "regtile", 0, 5, args=args, from_zero=True)
+    st.apply(circ, "auto", args=args, from_zero=True)
+    for _ in range(8):
+        st.apply(circ, "auto", args=args, from_zero=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(3):
-        st.apply(circ, "regtile", 0, 5, args=args, from_zero=True)
+    for _ in range(5):
+        st.apply(circ, "auto", args=args, from_zero=True)
     torch.cuda.synchronize()
-    fwd = (time.perf_counter() - t0) / 3
+    fwd = (time.perf_counter() - t0) / 5
     out = {"workload": "5x5 grid, 25 qubits, depth 30, %d parametrised gates, complex64, 1e4 samples"
                        % circ.nparams, "forward_s": round(fwd, 5)}
-    for ck in (0, 5, 10):
-        st.backward(circ, xs, checkpoint_c=ck)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        loss, g = st.backward(circ, xs, checkpoint_c=ck)
-        dt = time.perf_counter() - t0
-        out["c%d" % ck] = {"grad_s": round(dt, 5), "grad_over_fwd": round(dt / fwd, 3), "loss": loss}
-        log("grad c=%d: %.4f s (fwd %.4f s)" % (ck, dt, fwd))
+    for tile in (4, 5):
+        for ck, ready in ((0, True), (0, False), (5, False), (10, False)):
+            def once():
+                if ready:
+                    st.apply(circ, "auto", args=args, from_zero=True)
+                    torch.cuda.synchronize()
+                t = time.perf_counter()
+                r = st.backward(circ, xs, checkpoint_c=ck, tile=tile, state_ready=ready)
+                return time.perf_counter() - t, r
+            once()
+            best = None
+            for _ in range(3):
+                dt, (loss, g) = once()
+                best = dt if best is None else min(best, dt)
+            key = "%s_c%d_t%d" % ("ready" if ready else "full", ck, tile)
+            out[key] = {"grad_s": round(best, 5), "grad_over_fwd": round(best / fwd, 3), "loss": loss}
+            log("grad %s: %.4f s (fwd %.4f s)" % (key, best, fwd))
     st.close()
     return out
 

@@ -162,7 +162,9 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
                                                        const uint8_t *__restrict__ prog, uint64_t ntiles,
                                                        double *__restrict__ gpart, int nslots) {
     constexpr int NR = 1 << VB;
-    const RTHeader *h = reinterpret_cast<const RTHeader *>(prog);
+    // the program is read-only while the kernel runs: scalar loads through
+    // the constant address space, also after the gradient stores
+    const cptr<RTHeader> h = (cptr<RTHeader>)prog;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t tile = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
@@ -182,8 +184,8 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
         phi[r] = gload<T>(uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r))) + lane);
         mu[r] = gload<T>(uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r))) + lane);
     }
-    const RTOp *ops = reinterpret_cast<const RTOp *>(prog + h->op_off);
-    const DiagTerm *terms = reinterpret_cast<const DiagTerm *>(prog + h->term_off);
+    const cptr<RTOp> ops = (cptr<RTOp>)(prog + h->op_off);
+    const cptr<DiagTerm> terms = (cptr<DiagTerm>)(prog + h->term_off);
     const int nops = h->nops;
     for (int o = 0; o < nops; o++) {
         const int kind = ops[o].kind;

@@ -1,0 +1,114 @@
+"""Full-size GPU checks: the 35-qubit, depth-40 circuit of the 5x7 grid in
+complex64 (a 256 GiB state), checked through properties that hold at any
+size, since no reference can hold the state:
+
+* the Clifford variant (T replaced by S) against a stabilizer tableau: the
+  probability of every sampled bit string is exactly 2^-r, the entropy is
+  r ln 2 and 2^n - 2^r outcomes have probability zero;
+* the circuit followed by its inverse returns |0...0>;
+* the output of the circuit itself is Porter-Thomas distributed (Sec. IV):
+  entropy ln N - 1 + gamma, moments M_k -> k!, and 10^6 samples drawn from
+  it have cross entropy equal to the entropy (Delta H = 1 up to the sample
+  error).
+
+The 30-qubit FP64 reference comparison of the same family takes minutes on
+the host and runs only when SV_RUN_LARGE=1 is set.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1608_00263_amd import circuits as C
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1608_00263_amd import sv  # noqa: E402
+
+EULER_GAMMA = 0.5772156649015329
+N35_BYTES = 8 * 2 ** 35
+
+
+def _free_bytes():
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info(0)
+    return free
+
+
+@pytest.fixture(scope="module")
+def st35():
+    if _free_bytes() < N35_BYTES + (4 << 30):
+        pytest.skip("a 35-qubit complex64 state needs 260 GiB of free device memory")
+    print("allocating the 35-qubit state", flush=True)
+    st = sv.State(35, "c64")
+    yield st
+    st.close()
+    del st
+    torch.cuda.empty_cache()
+
+
+def test_c5_clifford_variant_vs_tableau(st35):
+    from tests.stabilizer import run_clifford
+    circ = C.make_circuit(5, 7, 40, seed=5, clifford=True)
+    print("clifford variant: %d gates" % circ.ngates, flush=True)
+    st35.apply(circ, "regtile", 0, 6, from_zero=True)
+    m = st35.moments()
+    tab = run_clifford(circ)
+    r = tab.num_random()
+    assert abs(m["norm"] - 1.0) < 1e-5
+    assert abs(m["entropy"] - r * math.log(2.0)) < 1e-4
+    assert m["zero_count"] == 2 ** 35 - 2 ** r
+    xs = st35.sample(64, 77)
+    for x in xs:
+        bits = [(int(x) >> q) & 1 for q in range(35)]
+        want = tab.probability(bits)
+        got = float(st35.probs(int(x), 1).cpu()[0])
+        assert want == 2.0 ** -r
+        assert abs(got / want - 1.0) < 1e-4, (int(x), got, want)
+
+
+def test_c5_circuit_then_inverse_is_identity(st35):
+    circ = C.make_circuit(5, 7, 40, seed=5)
+    st35.apply(circ, "regtile", 0, 6, from_zero=True)
+    st35.apply(circ.inverse(), "regtile", 0, 6)
+    p0 = float(st35.probs(0, 1).cpu()[0])
+    m = st35.moments()
+    assert abs(m["norm"] - 1.0) < 1e-5
+    assert p0 > 1.0 - 1e-4
+
+
+def test_c5_porter_thomas_and_sample_cross_entropy(st35):
+    circ = C.make_circuit(5, 7, 40, seed=5)
+    st35.apply(circ, "regtile", 0, 6, from_zero=True)
+    m = st35.moments()
+    n = 35
+    assert abs(m["norm"] - 1.0) < 1e-5
+    assert abs(m["entropy"] - (n * math.log(2.0) - 1.0 + EULER_GAMMA)) < 2e-3
+    for k in range(1, 6):
+        assert abs(m["moments"][k - 1] / math.factorial(k) - 1.0) < 0.02 * k
+    xs = st35.sample(10 ** 6, 1005)
+    ce, dh, z = st35.cross_entropy(xs)
+    assert z == 0
+    # mean of -ln p over samples from p: the entropy, with a standard error
+    # of about 1.3 / sqrt(10^6)
+    assert abs(ce - m["entropy"]) < 6e-3
+    assert abs(dh - 1.0) < 8e-3
+
+
+@pytest.mark.skipif(os.environ.get("SV_RUN_LARGE") != "1",
+                    reason="the 30-qubit FP64 reference run takes minutes (set SV_RUN_LARGE=1)")
+def test_c2_shape_seed5_vs_reference_30q():
+    import oracle
+    circ = C.make_circuit(5, 6, 40, seed=5)
+    print("reference run, 30 qubits complex128", flush=True)
+    ref = oracle.apply_circuit(circ)
+    st = sv.State(30, "c64")
+    st.apply(circ, "auto", from_zero=True)
+    got = st.amplitudes()
+    st.close()
+    assert np.linalg.norm(got - ref) <= 1e-4
