@@ -197,7 +197,7 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
                 const int gk = ops[o].gkind;
                 double g = kind == RT_REG ? grad_reg_dispatch<T, NR>(phi, mu, d, arg, gk)
                                           : grad_lane_dispatch<T, NR>(phi, mu, d, arg, lane, gk);
-                g = wave_sum_d<T>(g);
+                g = wave_sum_d<T>(g) * ops[o].gscale;
                 if (lane == 0) gpart[tile * (uint64_t)nslots + slot] = g;
             }
             const Mat2<T> u = load_mat<T>(ops[o].u);
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
 #pragma unroll
                 for (int r = 0; r < NR; r++)
                     if ((rs >> r) & 1) g += (double)re_cm(mu[r], cmul(dv, phi[r]));
-                g = wave_sum_d<T>(g);
+                g = wave_sum_d<T>(g) * ops[o].gscale;
                 if (lane == 0) gpart[tile * (uint64_t)nslots + slot] = g;
             }
             cplx<T> v;
@@ -250,6 +250,16 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
                     phi[r] = cmul(v, phi[r]);
                     mu[r] = cmul(v, mu[r]);
                 }
+        }
+    }
+    // the cosines taken out of the tangent-form rotations
+    const double fs = h->fscale;
+    if (fs != 1.0) {
+        const T f = (T)fs;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            phi[r].re *= f; phi[r].im *= f;
+            mu[r].re *= f; mu[r].im *= f;
         }
     }
 #pragma unroll

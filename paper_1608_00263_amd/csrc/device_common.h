@@ -111,6 +111,14 @@ __device__ __forceinline__ void pair_form(cplx<T> &x, cplx<T> &y, const Mat2<T> 
     } else if constexpr (FORM == F_REAL) {
         x.re = fma(u.m[0].re, a.re, u.m[1].re * b.re); x.im = fma(u.m[0].re, a.im, u.m[1].re * b.im);
         y.re = fma(u.m[2].re, a.re, u.m[3].re * b.re); y.im = fma(u.m[2].re, a.im, u.m[3].re * b.im);
+    } else if constexpr (FORM == F_TRX) {      // x - i t y, -i t x + y
+        const T t = -u.m[1].im;
+        x.re = fma(t, b.im, a.re); x.im = fma(-t, b.re, a.im);
+        y.re = fma(t, a.im, b.re); y.im = fma(-t, a.re, b.im);
+    } else if constexpr (FORM == F_TRY) {      // x - t y, t x + y
+        const T t = u.m[2].re;
+        x.re = fma(-t, b.re, a.re); x.im = fma(-t, b.im, a.im);
+        y.re = fma(t, a.re, b.re); y.im = fma(t, a.im, b.im);
     } else {                                   // F_PHASE
         y = cmul(u.m[3], b);
     }
@@ -137,6 +145,8 @@ __device__ __forceinline__ void reg_gate_s(cplx<T> (&a)[NR], const Mat2<T> &u, i
     case F_RX: reg_gate_f<T, NR, S, F_RX>(a, u); break;
     case F_RY: reg_gate_f<T, NR, S, F_RY>(a, u); break;
     case F_REAL: reg_gate_f<T, NR, S, F_REAL>(a, u); break;
+    case F_TRX: reg_gate_f<T, NR, S, F_TRX>(a, u); break;
+    case F_TRY: reg_gate_f<T, NR, S, F_TRY>(a, u); break;
     default: reg_gate_f<T, NR, S, F_GEN>(a, u); break;
     }
 }
@@ -234,6 +244,10 @@ __device__ __forceinline__ void lane_gate_f(cplx<T> (&a)[NR], const Mat2<T> &u, 
     } else if constexpr (FORM == F_REAL) {
         rc = hi ? u.m[3].re : u.m[0].re;
         rs = hi ? u.m[2].re : u.m[1].re;    // cs self + cp p
+    } else if constexpr (FORM == F_TRX) {
+        rs = -u.m[1].im;            // self - i t p (both halves)
+    } else if constexpr (FORM == F_TRY) {
+        rs = hi ? u.m[2].re : -u.m[2].re;   // lo: self - t p, hi: self + t p
     } else if constexpr (FORM == F_H) {
         sg = hi ? (T)-1 : (T)1;     // lo: self + p, hi: p - self
     } else if constexpr (FORM == F_SY) {
@@ -259,6 +273,10 @@ __device__ __forceinline__ void lane_gate_f(cplx<T> (&a)[NR], const Mat2<T> &u, 
             o.re = s.re - p.im; o.im = s.im + p.re;
         } else if constexpr (FORM == F_RX) {
             o.re = fma(rc, s.re, rs * p.im); o.im = fma(rc, s.im, -rs * p.re);
+        } else if constexpr (FORM == F_TRX) {
+            o.re = fma(rs, p.im, s.re); o.im = fma(-rs, p.re, s.im);
+        } else if constexpr (FORM == F_TRY) {
+            o.re = fma(rs, p.re, s.re); o.im = fma(rs, p.im, s.im);
         } else {                                 // F_RY, F_REAL
             o.re = fma(rc, s.re, rs * p.re); o.im = fma(rc, s.im, rs * p.im);
         }
@@ -278,6 +296,8 @@ __device__ __forceinline__ void lane_gate_b(cplx<T> (&a)[NR], const Mat2<T> &u, 
     case F_RX: lane_gate_f<T, NR, B, F_RX>(a, u, lane); break;
     case F_RY: lane_gate_f<T, NR, B, F_RY>(a, u, lane); break;
     case F_REAL: lane_gate_f<T, NR, B, F_REAL>(a, u, lane); break;
+    case F_TRX: lane_gate_f<T, NR, B, F_TRX>(a, u, lane); break;
+    case F_TRY: lane_gate_f<T, NR, B, F_TRY>(a, u, lane); break;
     default: lane_gate_f<T, NR, B, F_GEN>(a, u, lane); break;
     }
 }
@@ -434,6 +454,16 @@ __device__ __forceinline__ void regtile_apply(cplx<T> *__restrict__ psi, const u
         for (int r = 0; r < NR; r++) {
             a[r].re *= rs;
             a[r].im *= rs;
+        }
+    }
+    // the cosines taken out of the tangent-form rotations
+    const double fs = h->fscale;
+    if (fs != 1.0) {
+        const T f = (T)fs;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            a[r].re *= f;
+            a[r].im *= f;
         }
     }
 #pragma unroll

@@ -101,7 +101,7 @@ static void emulate_regtile(const Plan &plan, const Op &op, int n, cx *psi) {
                 }
             }
         }
-        const double sc = std::ldexp(1.0, h->sexp) * (h->shalf ? 1.0 / std::sqrt(2.0) : 1.0);
+        const double sc = std::ldexp(1.0, h->sexp) * (h->shalf ? 1.0 / std::sqrt(2.0) : 1.0) * h->fscale;
         for (int l = 0; l < 64; l++)
             for (int r = 0; r < nr; r++) psi[base + roff[r] + l] = a[l * nr + r] * sc;
     }
@@ -289,9 +289,9 @@ extern "C" sv_status sv_host_plan_describe(const sv_circuit *c, sv_dtype dt, con
             const RTHeader *h = (const RTHeader *)(plan.prog.data() + op.prog_off);
             const RTOp *ops = (const RTOp *)((const uint8_t *)h + h->op_off);
             int nreg = 0, nlane = 0, nsign = 0, nterm = 0, nphase = 0;
-            int nform[10] = {0};
+            int nform[12] = {0};
             for (int o = 0; o < h->nops; o++) {
-                if (ops[o].kind == RT_REG || ops[o].kind == RT_LANE) nform[std::min(9, std::max(0, (int)ops[o].form))]++;
+                if (ops[o].kind == RT_REG || ops[o].kind == RT_LANE) nform[std::min(11, std::max(0, (int)ops[o].form))]++;
                 if (ops[o].kind == RT_REG) nreg++;
                 else if (ops[o].kind == RT_LANE) nlane++;
                 else if (ops[o].kind == RT_SIGNS) { nsign++; nterm += ops[o].nterms; }
@@ -300,8 +300,9 @@ extern "C" sv_status sv_host_plan_describe(const sv_circuit *c, sv_dtype dt, con
             std::string rq;
             for (int j = 0; j < h->vbits; j++) rq += (j ? "," : "") + std::to_string(h->rq[j]);
             std::string fs;
-            static const char *fname[10] = {"gen", "h", "sx", "sy", "sxdg", "sydg", "phase", "rx", "ry", "real"};
-            for (int f = 0; f < 10; f++)
+            static const char *fname[12] = {"gen", "h", "sx", "sy", "sxdg", "sydg", "phase", "rx", "ry", "real",
+                                            "trx", "try"};
+            for (int f = 0; f < 12; f++)
                 if (nform[f]) fs += std::string(fs.empty() ? "" : ",") + fname[f] + ":" + std::to_string(nform[f]);
             snprintf(line, sizeof line, "%zu regtile v=%d rq=[%s] reg=%d lane=%d signops=%d cz=%d phase=%d forms=[%s]\n",
                      i, h->vbits, rq.c_str(), nreg, nlane, nsign, nterm, nphase, fs.c_str());

@@ -83,6 +83,10 @@ enum RTForm : int32_t {
     F_RX = 7,       // [[c, -i s], [-i s, c]]   (c = u00, s = -Im u01)
     F_RY = 8,       // [[c, -s], [s, c]]         (c = u00, s = u10)
     F_REAL = 9,     // real 2x2 matrix
+    // rotations divided by their cosine c (the factors c of a sweep are
+    // applied once, as RTHeader::fscale, when the tile is stored)
+    F_TRX = 10,     // [[1, -i t], [-i t, 1]]  (t = -Im u01)
+    F_TRY = 11,     // [[1, -t], [t, 1]]       (t = u10)
 };
 
 // True for the forms that carry a factor sqrt2.
@@ -101,7 +105,8 @@ struct RTOp {               // 160 bytes
     double d[8];            // adjoint: derivative generator D (dU = D U)
     int32_t form;           // RTForm
     int32_t gkind;          // GradKind of the generator
-    int32_t pad[2];
+    double gscale;          // adjoint: factor of the gradient share (the
+                            // square of the cosines applied before it)
 };
 
 // A diagonal term: amplitude x is multiplied by `val` (or negated for
@@ -117,7 +122,7 @@ struct DiagTerm {           // 48 bytes
     uint64_t pad2;
 };
 
-struct RTHeader {           // 64 bytes
+struct RTHeader {           // 80 bytes
     int32_t nops;
     int32_t vbits;
     int32_t rq[8];          // register qubits, ascending
@@ -128,6 +133,9 @@ struct RTHeader {           // 64 bytes
     int32_t shalf;          // ... and by 1/sqrt2 when set
     int32_t gen_n;          // > 0: do not load; start from the uniform state
                             // 2^{-gen_n/2} of gen_n qubits (Hadamard layer)
+    double fscale;          // store: amplitudes also scaled by fscale (the
+                            // product of the cosines of the F_TRX/F_TRY ops)
+    int32_t pad[2];
 };
 
 // LDS-tile ops

@@ -217,8 +217,11 @@ void fold_diagonals(std::vector<SGate> *gl, int n, bool param_safe, bool keep_ch
                 if (target >= 0 && param_safe && g[target].slot >= 0) target = -1;
             }
             if (target < 0) continue;   // no dense gate on q: stays a phase
-            // a gate with an add-only form costs less kept apart from the phase
-            if (keep_cheap && form_scaled(g[target].form)) continue;
+            // a gate with an add-only or rotation (tangent) form costs less
+            // kept apart from the phase
+            if (keep_cheap && (form_scaled(g[target].form) || g[target].form == F_RX ||
+                               g[target].form == F_RY))
+                continue;
             M2 d = g[i].u;
             g[target].u = before ? m2_mul(g[target].u, d) : m2_mul(d, g[target].u);
             g[target].form = is_real(g[target].u) ? F_REAL : F_GEN;
@@ -358,7 +361,23 @@ struct RTProgram {
     RTHeader h{};
     std::vector<RTOp> ops;
     std::vector<DiagTerm> terms;
+    std::vector<double> opc;   // cosine taken out of each op (1: none)
+    RTProgram() { h.fscale = 1.0; }
 };
+
+// A rotation [[c, -i s], [-i s, c]] or [[c, -s], [s, c]] applied as its
+// tangent form (the matrix divided by c): two fused multiply-adds per pair
+// component instead of a product and a fused multiply-add.  Taken only
+// while |t| = |s / c| <= sqrt(3), so that no term grows large.
+static bool tangent_form(RTOp *o, double *c_out) {
+    if (o->form != F_RX && o->form != F_RY) return false;
+    const double c = o->u[0];   // Re u00
+    if (!(std::fabs(c) >= 0.5)) return false;
+    for (int i = 0; i < 8; i++) o->u[i] /= c;
+    o->form = o->form == F_RX ? F_TRX : F_TRY;
+    *c_out = c;
+    return true;
+}
 
 static void put_mat(double *dst, const M2 &m) {
     for (int i = 0; i < 4; i++) { dst[2 * i] = m.m[i].re; dst[2 * i + 1] = m.m[i].im; }
@@ -459,6 +478,7 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
             put_mat(o.d, s.d);
             o.form = s.form;
             o.gkind = s.gkind;
+            o.gscale = 1.0;
             if (s.kind == SG_DENSE && form_scaled(s.form)) {
                 if (cheap) {
                     nc++;
@@ -468,7 +488,10 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
                            : (s.form == F_SY || s.form == F_SYDG) ? F_RY : F_REAL;
                 }
             }
+            double c = 1.0;
+            if (s.kind == SG_DENSE && tangent_form(&o, &c)) h.fscale *= c;
             ops.push_back(o);
+            P.opc.push_back(c);
         } else if (s.kind == SG_CZ) {
             DiagTerm t = term_for(bit64(s.q0) | bit64(s.q1));
             if (!ops.empty() && ops.back().kind == RT_SIGNS &&
@@ -480,7 +503,9 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
                 o.a = (int)terms.size();
                 o.nterms = 1;
                 o.slot = -1;
+                o.gscale = 1.0;
                 ops.push_back(o);
+                P.opc.push_back(1.0);
             }
             terms.push_back(t);
         } else {
@@ -498,9 +523,11 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
             o.nterms = 1;
             o.slot = s.slot;
             o.gkind = s.gkind;
+            o.gscale = 1.0;
             put_mat(o.d, s.d);
             terms.push_back(t);
             ops.push_back(o);
+            P.opc.push_back(1.0);
             if (d0.re != 1.0 || d0.im != 0.0) {
                 DiagTerm all = term_for(0);
                 all.val[0] = d0.re;
@@ -510,8 +537,10 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
                 o2.a = (int)terms.size();
                 o2.nterms = 1;
                 o2.slot = -1;
+                o2.gscale = 1.0;
                 terms.push_back(all);
                 ops.push_back(o2);
+                P.opc.push_back(1.0);
             }
         }
     }
@@ -540,12 +569,19 @@ static void assign_scales(Plan *plan, const std::vector<std::pair<size_t, int>> 
 static RTProgram reverse_regtile(const RTProgram &F) {
     RTProgram B = F;
     std::reverse(B.ops.begin(), B.ops.end());
-    for (RTOp &o : B.ops) {
+    std::reverse(B.opc.begin(), B.opc.end());
+    // the tangent forms leave both states short of the cosines applied so
+    // far in this sweep: a gradient share is scaled by their square
+    double k = 1.0;
+    for (size_t i = 0; i < B.ops.size(); i++) {
+        RTOp &o = B.ops[i];
+        o.gscale = k * k;
         if (o.kind == RT_REG || o.kind == RT_LANE) {
             M2 u;
-            for (int i = 0; i < 4; i++) u.m[i] = {o.u[2 * i], o.u[2 * i + 1]};
+            for (int j = 0; j < 4; j++) u.m[j] = {o.u[2 * j], o.u[2 * j + 1]};
             put_mat(o.u, m2_dag(u));
         }
+        k *= B.opc[i];
     }
     for (DiagTerm &t : B.terms) t.val[1] = -t.val[1];
     return B;
@@ -841,9 +877,9 @@ static void plan_per_gate(const sv_circuit *c, const std::vector<SGate> &g, cons
 // Register-tile grouping with an arithmetic budget per sweep.  Costs are
 // vector instructions per amplitude register of a lane (the sweep's memory
 // time allows about 110 of them at complex64 and twice that at complex128):
-// add-only forms 2 on a register qubit and 5 on a lane qubit (cross-lane
-// moves), general 2x2 gates 8 and 11, phases 2 (register) or 4, and 1 per CZ
-// sign flip.
+// add-only and rotation (tangent) forms 2 on a register qubit and 5 on a
+// lane qubit (cross-lane moves), general 2x2 gates 8 and 11, phases 2
+// (register) or 4, and 1 per CZ sign flip.
 static std::vector<Sweep> regtile_sweeps(const std::vector<SGate> &g, int n, int vb, int dtype,
                                          double budget = -1) {
     if (budget < 0) budget = dtype == SV_C64 ? 110.0 : 220.0;
@@ -853,9 +889,9 @@ static std::vector<Sweep> regtile_sweeps(const std::vector<SGate> &g, int n, int
         const bool lane = s.q0 < LANE_BITS;
         const bool reg = !lane && in_tile[s.q0];
         if (s.kind == SG_DIAG1) return reg ? 2.0 : 4.0;
-        if (form_scaled(s.form)) return lane ? 5.0 : 2.0;
+        if (form_scaled(s.form) || s.form == F_RX || s.form == F_RY) return lane ? 5.0 : 2.0;
         if (s.form == F_GEN) return lane ? 11.0 : 8.0;
-        return lane ? 7.0 : 4.0;   // rotation and real forms
+        return lane ? 7.0 : 4.0;   // real forms
     };
     return group_sweeps(
         (int)g.size(), n, vb, [&](int i) { return g[i].kind != SG_DENSE; },
