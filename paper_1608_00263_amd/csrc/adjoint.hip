@@ -24,11 +24,31 @@
 
 namespace svi {
 
+// Sum over the 64 lanes of a wavefront, the same in every lane.  Complex64
+// states sum their gradient shares in FP32 by a butterfly of DPP moves
+// (lane bits 0..3) and register half-swaps (bits 4, 5); complex128 states
+// in FP64 through the lane shuffles.
 template <typename T>
-__device__ __forceinline__ double wave_sum_d(double v) {
+__device__ __forceinline__ double wave_sum_d(double g) {
+    if constexpr (sizeof(T) == 4) {
+        float v = (float)g;
+        v += lane_xor<0>(v);
+        v += lane_xor<1>(v);
+        v += lane_xor<2>(v);
+        v += lane_xor<3>(v);
+        int a = __float_as_int(v), b = a;
+        half_swap_i<4>(a, b);
+        v = __int_as_float(a) + __int_as_float(b);
+        a = __float_as_int(v);
+        b = a;
+        half_swap_i<5>(a, b);
+        v = __int_as_float(a) + __int_as_float(b);
+        return (double)v;
+    } else {
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+        for (int m = 32; m >= 1; m >>= 1) g += __shfl_xor(g, m, 64);
+        return g;
+    }
 }
 
 // Im conj(a) b and Re conj(a) b
@@ -157,6 +177,51 @@ __device__ __forceinline__ double grad_lane_dispatch(const cplx<T> (&phi)[NR], c
     }
 }
 
+// A rotation in tangent form on lane bit 4 or 5 with its gradient share,
+// phi and mu together: register half-swaps give every lane whole pairs of
+// both states, so the share is lane-local (no cross-lane moves beyond the
+// swaps the gate needs anyway).  G_RX share (1/2)[Im conj(mu0) phi1 +
+// Im conj(mu1) phi0], G_RY share (1/2)[Re conj(mu1) phi0 - Re conj(mu0)
+// phi1], taken before the gate.
+template <typename T, int NR, int B, int FORM>
+__device__ __forceinline__ double lane_rot_grad_gate(cplx<T> (&phi)[NR], cplx<T> (&mu)[NR], const Mat2<T> &u) {
+    static_assert(B == 4 || B == 5, "half swaps exist for lane bits 4 and 5");
+    T acc = 0;
+#pragma unroll
+    for (int r = 0; r < NR; r += 2) {
+        cplx<T> x = phi[r], y = phi[r + 1], mx = mu[r], my = mu[r + 1];
+        half_swap<B>(x.re, y.re);
+        half_swap<B>(x.im, y.im);
+        half_swap<B>(mx.re, my.re);
+        half_swap<B>(mx.im, my.im);
+        if constexpr (FORM == F_TRX) acc += im_cm(mx, y) + im_cm(my, x);
+        else acc += re_cm(my, x) - re_cm(mx, y);
+        pair_form<T, FORM>(x, y, u);
+        pair_form<T, FORM>(mx, my, u);
+        half_swap<B>(x.re, y.re);
+        half_swap<B>(x.im, y.im);
+        half_swap<B>(mx.re, my.re);
+        half_swap<B>(mx.im, my.im);
+        phi[r] = x;
+        phi[r + 1] = y;
+        mu[r] = mx;
+        mu[r + 1] = my;
+    }
+    return 0.5 * (double)acc;
+}
+
+template <typename T, int NR>
+__device__ __forceinline__ double lane_rot_dispatch(cplx<T> (&phi)[NR], cplx<T> (&mu)[NR], const Mat2<T> &u,
+                                                    int b, int form) {
+    if constexpr (NR >= 2) {
+        if (b == 4) return form == F_TRX ? lane_rot_grad_gate<T, NR, 4, F_TRX>(phi, mu, u)
+                                         : lane_rot_grad_gate<T, NR, 4, F_TRY>(phi, mu, u);
+        return form == F_TRX ? lane_rot_grad_gate<T, NR, 5, F_TRX>(phi, mu, u)
+                             : lane_rot_grad_gate<T, NR, 5, F_TRY>(phi, mu, u);
+    }
+    return 0.0;
+}
+
 template <typename T, int VB>
 __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi_g, cplx<T> *__restrict__ mu_g,
                                                        const uint8_t *__restrict__ prog, uint64_t ntiles,
@@ -191,7 +256,19 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
         const int kind = ops[o].kind;
         const int arg = ops[o].a;
         const int slot = ops[o].slot;
-        if (kind == RT_REG || kind == RT_LANE) {
+        const int form0 = ops[o].form;
+        const int gk0 = ops[o].gkind;
+        // (a branch condition without short-circuit jumps keeps the op
+        // dispatch free of merged register flows)
+        const int fused = __builtin_amdgcn_readfirstlane(
+            (int)((kind == RT_LANE) & (slot >= 0) & (arg >= 4) & (NR >= 2) &
+                  (((form0 == F_TRX) & (gk0 == G_RX)) | ((form0 == F_TRY) & (gk0 == G_RY)))));
+        if (fused) {
+            const Mat2<T> u = load_mat<T>(ops[o].u);
+            double g = lane_rot_dispatch<T, NR>(phi, mu, u, arg, form0);
+            g = wave_sum_d<T>(g) * ops[o].gscale;
+            if (lane == 0) gpart[tile * (uint64_t)nslots + slot] = g;
+        } else if (kind == RT_REG || kind == RT_LANE) {
             if (slot >= 0) {
                 const Mat2<T> d = load_mat<T>(ops[o].d);
                 const int gk = ops[o].gkind;
@@ -295,11 +372,11 @@ __global__ __launch_bounds__(BLOCK) void k_zero(cplx<T> *__restrict__ v, uint64_
     }
 }
 
-// Gradient slot sums, two levels in a fixed order: chunk c of 256 tiles is
+// Gradient slot sums, two levels in a fixed order: chunk c of 64 tiles is
 // summed serially per slot (threads over slots, coalesced rows), then the
 // chunk partials are combined in chunk order with Neumaier's summation and
 // scaled by -2.
-constexpr int GCHUNK = 256;
+constexpr int GCHUNK = 64;
 
 __global__ __launch_bounds__(256) void k_grad_partial(const double *__restrict__ gpart, uint64_t ntiles,
                                                       int nslots, double *__restrict__ part) {
