@@ -30,6 +30,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_regtile_c2_traffic.txt")
+# sources of the register-tile sweep and its programs: the counter-based
+# traffic of the profile summary is reported only while these are unchanged
+KERNEL_SOURCES = ["paper_1608_00263_amd/csrc/device_common.h", "paper_1608_00263_amd/csrc/sweeps.hip",
+                  "paper_1608_00263_amd/csrc/internal.h", "paper_1608_00263_amd/csrc/plan.cpp"]
+
+
+def kernel_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(tile):
+    """HBM bytes per register-tile launch from the committed counter summary,
+    or None when the summary is missing, for another tile width, or older
+    than the kernel sources."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_sha1") != kernel_sha1() or int(kv.get("register_qubits", -1)) != tile:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -157,10 +189,11 @@ def main():
         "sweep_GBps": round(sweep_bytes[-1] / (np.mean(sweep_ms) / 1e3) / 1e9, 2),
         "sweep_frac_of_peak": round(sweep_bytes[-1] / (np.mean(sweep_ms) / 1e3) / 1e9 / PEAK_HBM_GBPS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(a.tile if a.mode == "regtile" else -1),
                      "kernel": "k_regtile<float,%d>" % a.tile,
                      "launch_avg_ms": round(dom_ms / max(dom_launches, 1), 4),
-                     "bytes_per_launch": 2 * S64},
+                     "bytes_per_launch": round(dom_bytes / max(dom_launches, 1), 1),
+                     "kernel_sources_sha1": kernel_sha1()},
         "results": {"entropy": mom["entropy"], "unif_ce": mom["unif_ce"], "norm": mom["norm"],
                     "M2": mom["M2"], "M10": mom["M10"], "ce": ce, "delta_h": dh},
     }

@@ -88,18 +88,42 @@ __global__ __launch_bounds__(RB) void k_stats(const cpx<T> *__restrict__ psi, ui
 }
 
 // Combine per-workgroup partials in workgroup order (Neumaier).
-__global__ void k_combine(const double *__restrict__ part, int nblocks, int nq, double *__restrict__ out) {
-    const int q = threadIdx.x;
-    if (q >= nq) return;
+// Combine per-workgroup partial rows (16 doubles each) in row order with
+// Neumaier's summation, quantity q = 0..nq-1.  256 threads: 16 row segments
+// per quantity are summed in parallel, then the segment sums and their
+// compensations are combined in segment order (a fixed order: the result
+// does not depend on timing).
+__global__ __launch_bounds__(256) void k_combine(const double *__restrict__ part, int nblocks, int nq,
+                                                 double *__restrict__ out) {
+    __shared__ double ss[16][16], cc[16][16];
+    const int q = threadIdx.x & 15, seg = threadIdx.x >> 4;
+    const int per = (nblocks + 15) / 16;
+    const int b0 = seg * per, b1 = b0 + per < nblocks ? b0 + per : nblocks;
     double s = 0.0, c = 0.0;
-    for (int b = 0; b < nblocks; b++) {
-        const double x = part[(uint64_t)b * 16 + q];
-        const double t = s + x;
-        if (fabs(s) >= fabs(x)) c += (s - t) + x;
-        else c += (x - t) + s;
-        s = t;
+    if (q < nq) {
+        for (int b = b0; b < b1; b++) {
+            const double x = part[(uint64_t)b * 16 + q];
+            const double t = s + x;
+            if (fabs(s) >= fabs(x)) c += (s - t) + x;
+            else c += (x - t) + s;
+            s = t;
+        }
     }
-    out[q] = s + c;
+    ss[seg][q] = s;
+    cc[seg][q] = c;
+    __syncthreads();
+    if (threadIdx.x < nq) {
+        double S = 0.0, C = 0.0;
+        for (int g = 0; g < 16; g++) {
+            const double x = ss[g][threadIdx.x];
+            const double t = S + x;
+            if (fabs(S) >= fabs(x)) C += (S - t) + x;
+            else C += (x - t) + S;
+            S = t;
+            C += cc[g][threadIdx.x];
+        }
+        out[threadIdx.x] = S + C;
+    }
 }
 
 static void stats_grid(int n, int *nblocks, uint64_t *chunk) {
@@ -122,7 +146,7 @@ static sv_status stats_typed(sv_state *st, const void *psi, double *host16) {
     hipLaunchKernelGGL((k_stats<T, FULL>), dim3(nb), dim3(RB), 0, st->stream, (const cpx<T> *)psi,
                        chunk, std::ldexp(1.0, st->n), part);
     SV_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_combine, dim3(1), dim3(64), 0, st->stream, part, nb, FULL ? NSTAT + 1 : 1, res);
+    hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, st->stream, part, nb, FULL ? NSTAT + 1 : 1, res);
     SV_HIP(hipGetLastError());
     SV_HIP(hipMemcpyAsync(host16, res, 16 * sizeof(double), hipMemcpyDeviceToHost, st->stream));
     SV_HIP(hipStreamSynchronize(st->stream));
@@ -161,7 +185,7 @@ sv_status batch_stats_enqueue(sv_state *st, double *part, double *res) {
         hipLaunchKernelGGL((k_stats<double, true>), dim3(nb), dim3(RB), 0, st->stream,
                            (const cpx<double> *)st->data, chunk, std::ldexp(1.0, st->n), part);
     SV_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_combine, dim3(1), dim3(64), 0, st->stream, part, nb, NSTAT + 1, res);
+    hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, st->stream, part, nb, NSTAT + 1, res);
     SV_HIP(hipGetLastError());
     return SV_OK;
 }
@@ -209,19 +233,43 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i) {
     return z ^ (z >> 31);
 }
 
-// Per bucket of 2^bs entries: W_b = sum of weights (exact integer sum).
+// Buckets of 2^bs entries, split into sub-buckets of 2^sb entries (sb <= bs,
+// at most 64 per bucket).  One wavefront per sub-bucket: lane l sums entries
+// l, l + 64, ... (coalesced rows), the wave total is the exact integer sum of
+// the sub-bucket's weights; the workgroup then forms the bucket total from
+// its sub-bucket sums in order.
+constexpr int SUB_BITS = 10;   // 1024 entries per sub-bucket
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
 template <typename S>
-__global__ __launch_bounds__(RB) void k_bucket_weights(const S *__restrict__ src, int bs,
-                                                       unsigned long long *__restrict__ bsum) {
-    __shared__ unsigned long long red[4];
-    const uint64_t start = (uint64_t)blockIdx.x << bs;
-    const uint64_t len = 1ull << bs;
-    unsigned long long acc = 0;
-    for (uint64_t j = threadIdx.x; j < len; j += RB) acc += weight_of(prob_of(src[start + j]));
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+__global__ __launch_bounds__(RB) void k_bucket_weights(const S *__restrict__ src, int bs, int sb,
+                                                       unsigned long long *__restrict__ bsum,
+                                                       unsigned long long *__restrict__ subsum) {
+    __shared__ unsigned long long sh[64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nsub = 1 << (bs - sb);
+    const uint64_t slen = 1ull << sb;
+    for (int j = wave; j < nsub; j += RB / 64) {
+        const uint64_t start = ((uint64_t)blockIdx.x << bs) + ((uint64_t)j << sb);
+        unsigned long long acc = 0;
+        for (uint64_t e = lane; e < slen; e += 64) acc += weight_of(prob_of(src[start + e]));
+        acc = wave_sum_u64(acc);
+        if (lane == 0) {
+            subsum[(uint64_t)blockIdx.x * nsub + j] = acc;
+            sh[j] = acc;
+        }
+    }
     __syncthreads();
-    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int j = 0; j < nsub; j++) t += sh[j];
+        bsum[blockIdx.x] = t;
+    }
 }
 
 // Exclusive scan of n uint64 values into out[0..n], out[n] = total.  One
@@ -255,8 +303,7 @@ __global__ __launch_bounds__(1024) void k_scan(const unsigned long long *__restr
 __global__ __launch_bounds__(RB) void k_targets(const uint64_t *__restrict__ words, uint64_t seed,
                                                 int64_t k, const unsigned long long *__restrict__ off,
                                                 uint64_t nb, uint32_t *__restrict__ tb,
-                                                unsigned long long *__restrict__ tloc,
-                                                unsigned long long *__restrict__ counts) {
+                                                unsigned long long *__restrict__ tloc) {
     const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
     if (i >= k) return;
     const unsigned long long W = off[nb];
@@ -270,110 +317,65 @@ __global__ __launch_bounds__(RB) void k_targets(const uint64_t *__restrict__ wor
     const uint64_t b = lo - 1;
     tb[i] = (uint32_t)b;
     tloc[i] = t - off[b];
-    atomicAdd(&counts[b], 1ull);
 }
 
-__global__ __launch_bounds__(RB) void k_scatter(int64_t k, const uint32_t *__restrict__ tb,
-                                                const unsigned long long *__restrict__ bstart,
-                                                unsigned long long *__restrict__ cursor,
-                                                uint32_t *__restrict__ bucket) {
-    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
-    if (i >= k) return;
-    const uint32_t b = tb[i];
-    const unsigned long long pos = atomicAdd(&cursor[b], 1ull);
-    bucket[bstart[b] + pos] = (uint32_t)i;
+// Inclusive prefix sum over the 64 lanes (lane order).
+__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
 }
 
-// One workgroup per bucket holding samples.  The bucket (2^bs weights) is
-// read in rounds of RB * RS entries, coalesced into LDS; within a round
-// thread t owns the contiguous stretch [RS t, RS t + RS).  Stretch sums are
-// scanned in (round, thread) order, so stretch k covers entries
-// [RS k, RS k + RS) of the bucket.  Each sample then binary-searches the
-// stretch prefixes and walks one stretch to the first entry whose running
-// sum exceeds its target (x = min{j : C_j > t}).
-constexpr int RS = 16;                 // entries per stretch
-constexpr int RROUND = RB * RS;        // entries per round (4096)
-constexpr int MAXSTRETCH = (1 << 16) / RS;
-
+// One wavefront per sample: the sub-bucket holding the target (first
+// sub-bucket whose running sum exceeds it), then the lane run of R
+// consecutive entries holding it, then the entry: x = min{j : C_j > t}.
 template <typename S>
-__global__ __launch_bounds__(RB) void k_resolve(const S *__restrict__ src, int bs,
-                                                const unsigned long long *__restrict__ counts,
-                                                const unsigned long long *__restrict__ bstart,
-                                                const uint32_t *__restrict__ bucket,
-                                                const unsigned long long *__restrict__ tloc,
+__global__ __launch_bounds__(RB) void k_resolve(const S *__restrict__ src, int bs, int sb,
+                                                const unsigned long long *__restrict__ subsum,
+                                                const uint32_t *__restrict__ tb,
+                                                const unsigned long long *__restrict__ tloc, int64_t k,
                                                 uint64_t *__restrict__ out) {
-    const uint64_t b = blockIdx.x;
-    const unsigned long long cnt = counts[b];
-    if (cnt == 0) return;
-    __shared__ unsigned long long stage[RROUND];
-    __shared__ unsigned long long pre[MAXSTRETCH + 1];
-    const uint64_t len = 1ull << bs;
-    const int nstretch = (int)((len + RS - 1) / RS);
-    const uint64_t start = b << bs;
-    for (uint64_t r0 = 0; r0 < len; r0 += RROUND) {
-#pragma unroll
-        for (int i = 0; i < RS; i++) {
-            const uint64_t j = r0 + threadIdx.x + (uint64_t)i * RB;
-            stage[threadIdx.x + i * RB] = j < len ? weight_of(prob_of(src[start + j])) : 0ull;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (RB / 64) + (threadIdx.x >> 6);
+    if (i >= k) return;
+    const uint64_t b = tb[i];
+    const unsigned long long t = tloc[i];
+    const int nsub = 1 << (bs - sb);
+    // sub-bucket
+    const unsigned long long own = lane < nsub ? subsum[b * nsub + lane] : 0ull;
+    const unsigned long long incl = wave_incl_scan_u64(own, lane);
+    const unsigned long long above = __ballot(lane < nsub && incl > t);
+    int j = __ffsll((long long)above) - 1;
+    if (j < 0) j = nsub - 1;   // unreachable (t < bucket total); keeps every access in range
+    const unsigned long long before_j = __shfl(incl - own, j, 64);
+    const unsigned long long ts = t - before_j;
+    // lane runs of R entries inside sub-bucket j
+    const uint64_t start = (b << bs) + ((uint64_t)j << sb);
+    const int slen = 1 << sb;
+    const int R = slen >= 64 ? slen / 64 : 1;
+    const bool has = lane * R < slen;
+    unsigned long long run = 0;
+    if (has)
+        for (int e = 0; e < R; e++) run += weight_of(prob_of(src[start + (uint64_t)lane * R + e]));
+    const unsigned long long rincl = wave_incl_scan_u64(run, lane);
+    const unsigned long long hit = __ballot(has && rincl > ts);
+    int L = __ffsll((long long)hit) - 1;
+    if (L < 0) L = (slen >= 64 ? 64 : slen) - 1;   // unreachable (ts < sub-bucket total)
+    if (lane == L) {
+        unsigned long long c = rincl - run;
+        uint64_t ans = start + (uint64_t)lane * R + (R - 1);
+        for (int e = 0; e < R; e++) {
+            c += weight_of(prob_of(src[start + (uint64_t)lane * R + e]));
+            if (c > ts) {
+                ans = start + (uint64_t)lane * R + e;
+                break;
+            }
         }
-        __syncthreads();
-        const int k = (int)(r0 / RS) + threadIdx.x;
-        if (k < nstretch) {
-            unsigned long long s = 0;
-#pragma unroll
-            for (int i = 0; i < RS; i++) s += stage[threadIdx.x * RS + i];
-            pre[k + 1] = s;
-        }
-        __syncthreads();
+        out[i] = ans;
     }
-    // inclusive scan of stretch sums into pre[1..nstretch], pre[0] = 0
-    if (threadIdx.x == 0) pre[0] = 0;
-    __syncthreads();
-    {
-        const int per = (nstretch + RB - 1) / RB;
-        const int lo = threadIdx.x * per;
-        const int hi = lo + per < nstretch ? lo + per : nstretch;
-        unsigned long long run = 0;
-        for (int k = lo; k < hi; k++) { run += pre[k + 1]; pre[k + 1] = run; }
-        __shared__ unsigned long long tsum[RB];
-        tsum[threadIdx.x] = run;
-        __syncthreads();
-        if (threadIdx.x == 0)
-            for (int i = 1; i < RB; i++) tsum[i] += tsum[i - 1];
-        __syncthreads();
-        const unsigned long long add = threadIdx.x ? tsum[threadIdx.x - 1] : 0ull;
-        for (int k = lo; k < hi; k++) pre[k + 1] += add;
-    }
-    __syncthreads();
-    const unsigned long long b0 = bstart[b];
-    for (unsigned long long q = threadIdx.x; q < cnt; q += RB) {
-        const uint32_t smp = bucket[b0 + q];
-        const unsigned long long t = tloc[smp];
-        int lo = 0, hi = nstretch;   // last stretch with pre[k] <= t
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (pre[mid] <= t) lo = mid; else hi = mid;
-        }
-        unsigned long long run = pre[lo];
-        const uint64_t jb = (uint64_t)lo * RS;
-        const uint64_t je = jb + RS < len ? jb + RS : len;
-        uint64_t ans = je - 1;
-        for (uint64_t j = jb; j < je; j++) {
-            run += weight_of(prob_of(src[start + j]));
-            if (run > t) { ans = j; break; }
-        }
-        out[smp] = start + ans;
-    }
-}
-
-__global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
-}
-
-static unsigned cgrid(uint64_t items) {
-    uint64_t g = (items + RB - 1) / RB;
-    return (unsigned)(g < 65535 ? (g ? g : 1) : 65535);
 }
 
 template <typename S>
@@ -381,37 +383,30 @@ static sv_status sample_impl(Workspace *ws, hipStream_t s, const S *src, int n, 
                              uint64_t seed, int64_t k, uint64_t *dev_out) {
     if (k <= 0) return SV_OK;
     const int bs = n < 16 ? n : 16;
+    const int sb = bs < SUB_BITS ? bs : SUB_BITS;
     const uint64_t nb = 1ull << (n - bs);
+    const uint64_t nsubs = 1ull << (n - sb);
     size_t need = 0;
     auto take = [&](size_t bytes) { size_t o = need; need += (bytes + 255) & ~(size_t)255; return o; };
-    size_t o_bsum = take(nb * 8), o_off = take((nb + 1) * 8), o_cnt = take(nb * 8),
-           o_bst = take((nb + 1) * 8), o_cur = take(nb * 8), o_tb = take((size_t)k * 4),
-           o_tl = take((size_t)k * 8), o_bk = take((size_t)k * 4), o_w = take(8);
+    size_t o_bsum = take(nb * 8), o_off = take((nb + 1) * 8), o_sub = take(nsubs * 8),
+           o_tb = take((size_t)k * 4), o_tl = take((size_t)k * 8);
     SV_TRY(ws->reserve(need));
     uint8_t *w = (uint8_t *)ws->ptr;
     auto *bsum = (unsigned long long *)(w + o_bsum);
     auto *off = (unsigned long long *)(w + o_off);
-    auto *cnt = (unsigned long long *)(w + o_cnt);
-    auto *bst = (unsigned long long *)(w + o_bst);
-    auto *cur = (unsigned long long *)(w + o_cur);
+    auto *sub = (unsigned long long *)(w + o_sub);
     auto *tb = (uint32_t *)(w + o_tb);
     auto *tl = (unsigned long long *)(w + o_tl);
-    auto *bk = (uint32_t *)(w + o_bk);
-    (void)o_w;
-    hipLaunchKernelGGL((k_bucket_weights<S>), dim3((unsigned)nb), dim3(RB), 0, s, src, bs, bsum);
+    hipLaunchKernelGGL((k_bucket_weights<S>), dim3((unsigned)nb), dim3(RB), 0, s, src, bs, sb, bsum, sub);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, bsum, nb, off);
     unsigned long long W = 0;
     SV_HIP(hipMemcpyAsync(&W, off + nb, 8, hipMemcpyDeviceToHost, s));
     SV_HIP(hipStreamSynchronize(s));
     if (W == 0) return fail(SV_ESTATE, "sampler: every probability rounds to weight 0");
-    hipLaunchKernelGGL(k_zero_u64, dim3(cgrid(nb)), dim3(RB), 0, s, cnt, nb);
-    hipLaunchKernelGGL(k_zero_u64, dim3(cgrid(nb)), dim3(RB), 0, s, cur, nb);
     const unsigned kg = (unsigned)((k + RB - 1) / RB);
-    hipLaunchKernelGGL(k_targets, dim3(kg), dim3(RB), 0, s, words, seed, k, off, nb, tb, tl, cnt);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, cnt, nb, bst);
-    hipLaunchKernelGGL(k_scatter, dim3(kg), dim3(RB), 0, s, k, tb, bst, cur, bk);
-    hipLaunchKernelGGL((k_resolve<S>), dim3((unsigned)nb), dim3(RB), 0, s, src, bs, cnt, bst, bk, tl,
-                       dev_out);
+    hipLaunchKernelGGL(k_targets, dim3(kg), dim3(RB), 0, s, words, seed, k, off, nb, tb, tl);
+    const unsigned rg = (unsigned)((k + RB / 64 - 1) / (RB / 64));
+    hipLaunchKernelGGL((k_resolve<S>), dim3(rg), dim3(RB), 0, s, src, bs, sb, sub, tb, tl, k, dev_out);
     SV_HIP(hipGetLastError());
     return SV_OK;
 }
@@ -475,7 +470,7 @@ sv_status run_cross_entropy(sv_state *st, const void *psi, const uint64_t *dev_s
         hipLaunchKernelGGL(k_ce<double>, dim3((unsigned)nb), dim3(RB), 0, st->stream,
                            (const cpx<double> *)psi, mask, dev_samples, k, per, part);
     SV_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_combine, dim3(1), dim3(64), 0, st->stream, part, (int)nb, 2, res);
+    hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, st->stream, part, (int)nb, 2, res);
     double r[2];
     SV_HIP(hipMemcpyAsync(r, res, 2 * sizeof(double), hipMemcpyDeviceToHost, st->stream));
     SV_HIP(hipStreamSynchronize(st->stream));
