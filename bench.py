@@ -245,7 +245,7 @@ def mode_timings(sv, C, circ, torch):
             modes += [("fused", 4, 0, True), ("fused", 5, 0, True), ("regtile", 0, 4, False),
                       ("regtile", 0, 5, False), ("regtile", 0, 6, False)]
         else:
-            modes += [("regtile", 0, 3, False), ("regtile", 0, 4, False)]
+            modes += [("regtile", 0, 3, False), ("regtile", 0, 4, False), ("regtile", 0, 5, False)]
         modes += [("auto", 0, 0, False)]
         for mode, k, t, nomf in modes:
             st.apply(circ, mode, k, t, args=args, from_zero=True, no_mfma=nomf)   # plan + warm / tune
@@ -329,7 +329,7 @@ def ensemble_timings(sv, C, torch, count, reps=3):
     out = {"workload": "%d instances, grids 4x5/4x6/5x5, depth 20..40, complex64, %.1f GB of states"
                        % (count, state_bytes / 1e9)}
     runs = [("auto", {}), ("regtile_t4", dict(mode="regtile", tile=4)),
-            ("regtile_t5", dict(mode="regtile", tile=5)),
+            ("regtile_t5", dict(mode="regtile", tile=5)), ("regtile_t6", dict(mode="regtile", tile=6)),
             ("persistent_t5", dict(mode="regtile", tile=5, persistent=True)),
             ("launches_t5", dict(mode="regtile", tile=5, launches=True))]
     for label, kw in runs:

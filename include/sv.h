@@ -116,8 +116,9 @@ enum {
 typedef struct {
     int32_t mode;         /* SV_MODE_*                                        */
     int32_t k_max;        /* fused block width 1..5 (0 = default 4)           */
-    int32_t tile_qubits;  /* TILED: 8..13 (0 = default); REGTILE: register
-                             qubits 1..6 (0 = default)                        */
+    int32_t tile_qubits;  /* TILED: 8..13 (0 = default 12 / 11); REGTILE:
+                             register qubits 1..6 complex64, 1..5 complex128
+                             (0 = default 6 / 5)                              */
     int32_t flags;        /* SV_FLAG_* bits                                   */
     int32_t sweep_budget; /* REGTILE: vector instructions per amplitude
                              register one sweep may spend on gates before a
@@ -266,10 +267,11 @@ sv_status sv_backward(sv_state *st, const sv_circuit *c, const sv_opts *opts,
  * completion counters.  Either schedule is captured in a HIP graph that is
  * kept and replayed while the same handles, circuits and options come again
  * (one such graph per process).  The register-tile width is tile_qubits
- * (clamped to 3..5) under SV_MODE_REGTILE, else timed once on the largest
- * instance.  Everything else (complex128, other modes, smaller instances,
- * SV_FLAG_BATCH_LAUNCHES) runs as one captured graph of the ordinary
- * per-sweep launches.  SV_EDEVICE if a dependency wait of the persistent
+ * (clamped to 3..6) under SV_MODE_REGTILE, else the fastest of 4..6 timed
+ * on the ensemble itself, once per list of instance sizes (the timing runs
+ * write the same outputs).  Everything else (complex128, other modes,
+ * smaller instances, SV_FLAG_BATCH_LAUNCHES) runs as one captured graph of
+ * the ordinary per-sweep launches.  SV_EDEVICE if a dependency wait of the persistent
  * kernel exceeds its bound (the kernel still drains and exits; the states
  * are then unspecified). */
 sv_status sv_apply_batch(sv_state **sts, const sv_circuit *cs, int64_t count,

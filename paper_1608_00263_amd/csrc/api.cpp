@@ -90,7 +90,7 @@ static std::vector<sv_opts> tune_candidates(const sv_state *st) {
     auto add = [&](int mode, int k, int t) { c.push_back(sv_opts{mode, k, t, 0, 0}); };
     if (st->n >= 10) {
         if (st->dt == SV_C64) { add(SV_MODE_REGTILE, 0, 4); add(SV_MODE_REGTILE, 0, 5); add(SV_MODE_REGTILE, 0, 6); }
-        else { add(SV_MODE_REGTILE, 0, 3); add(SV_MODE_REGTILE, 0, 4); }
+        else { add(SV_MODE_REGTILE, 0, 3); add(SV_MODE_REGTILE, 0, 4); add(SV_MODE_REGTILE, 0, 5); }
         add(SV_MODE_FUSED, 2, 0);
         add(SV_MODE_FUSED, 3, 0);
         add(SV_MODE_TILED, 3, st->dt == SV_C64 ? 12 : 11);

@@ -247,50 +247,6 @@ static void finish_stats(const double *r, int n, sv_stats *o) {
     }
 }
 
-// Register-tile width of the ensemble (one kernel instantiation per width),
-// timed on the largest instance (its contents are overwritten by the
-// ensemble anyway).
-static sv_status choose_width(sv_state **sts, const sv_circuit *cs, int64_t count, int *vb_out) {
-    int64_t big = 0;
-    for (int64_t i = 1; i < count; i++)
-        if (sts[i]->n > sts[big]->n) big = i;
-    int best = 5;
-    float best_ms = -1;
-    for (int vb = 4; vb <= 5; vb++) {
-        PlanRequest rq{};
-        rq.n = sts[big]->n;
-        rq.dtype = SV_C64;
-        rq.mode = SV_MODE_REGTILE;
-        rq.tile = vb;
-        rq.from_zero = true;
-        rq.force_zero = true;
-        std::shared_ptr<Plan> plan;
-        SV_TRY(get_plan(sts[big], &cs[big], rq, &plan));
-        hipEvent_t a, b;
-        SV_HIP(hipEventCreate(&a));
-        SV_HIP(hipEventCreate(&b));
-        float ms = 0;
-        sv_status rc = SV_OK;
-        for (int rep = 0; rc == SV_OK && rep < 2; rep++) {
-            (void)hipEventRecord(a, sts[big]->stream);
-            for (const Op &op : plan->ops)
-                if (rc == SV_OK) rc = launch_op(sts[big], *plan, op, sts[big]->data);
-            (void)hipEventRecord(b, sts[big]->stream);
-            if (hipEventSynchronize(b) != hipSuccess) rc = fail(SV_EDEVICE, "width timing failed");
-            (void)hipEventElapsedTime(&ms, a, b);
-        }
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
-        SV_TRY(rc);
-        if (best_ms < 0 || ms < best_ms) {
-            best_ms = ms;
-            best = vb;
-        }
-    }
-    *vb_out = best;
-    return SV_OK;
-}
-
 static sv_status batch_graph_of_launches(sv_state **sts, const sv_circuit *cs, int64_t count,
                                          const sv_opts *opts, sv_stats *out);
 
@@ -411,8 +367,9 @@ static sv_status build_ensemble(sv_state **sts, const std::vector<std::shared_pt
     g->err = ctl + 2;
     g->res = (double *)(m + o_res);
     int per_cu = 0, dev = 0, ncu = 0;
-    auto kp = vb == 3 ? k_batch_persistent<3> : vb == 4 ? k_batch_persistent<4> : k_batch_persistent<5>;
-    auto kr = vb == 3 ? k_batch_round<3> : vb == 4 ? k_batch_round<4> : k_batch_round<5>;
+    auto kp = vb == 3 ? k_batch_persistent<3> : vb == 4 ? k_batch_persistent<4>
+            : vb == 5 ? k_batch_persistent<5> : k_batch_persistent<6>;
+    auto kr = vb == 3 ? k_batch_round<3> : vb == 4 ? k_batch_round<4> : vb == 5 ? k_batch_round<5> : k_batch_round<6>;
     if (persistent) {
         SV_HIP(hipGetDevice(&dev));
         SV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -466,44 +423,34 @@ extern "C" sv_status sv_apply_batch(sv_state **sts, const sv_circuit *cs, int64_
     if (!tables) return batch_graph_of_launches(sts, cs, count, opts, out);
     const bool persistent = opts && (opts->flags & SV_FLAG_BATCH_PERSISTENT);
 
-    // plans: register tiles from |0..0>, one width for the ensemble (timed
-    // once per largest qubit count)
-    static std::map<int, int> *width_of = new std::map<int, int>();   // kept for the process
-    int nmax = 0;
-    for (int64_t i = 0; i < count; i++) nmax = std::max(nmax, sts[i]->n);
-    int vb = 5;
-    if (opts && opts->mode == SV_MODE_REGTILE && opts->tile_qubits > 0) {
-        vb = std::min(5, std::max(3, opts->tile_qubits));
-    } else if (width_of->count(nmax)) {
-        vb = (*width_of)[nmax];
-    } else {
-        SV_TRY(choose_width(sts, cs, count, &vb));
-        (*width_of)[nmax] = vb;
-    }
-    std::vector<std::shared_ptr<Plan>> plans(count);
-    std::vector<const void *> key;
-    key.push_back((const void *)(intptr_t)(persistent ? 1 : 0));
-    key.push_back((const void *)(intptr_t)vb);
-    for (int64_t i = 0; i < count; i++) {
-        PlanRequest rq{};
-        rq.n = sts[i]->n;
-        rq.dtype = dt;
-        rq.mode = SV_MODE_REGTILE;
-        rq.tile = vb;
-        rq.from_zero = true;
-        rq.force_zero = true;
-        SV_TRY(get_plan(sts[i], &cs[i], rq, &plans[i]));
-        for (const Op &op : plans[i]->ops)
-            if (op.type != OP_REGTILE || op.vbits != vb) return batch_graph_of_launches(sts, cs, count, opts, out);
-        key.push_back(sts[i]->data);
-        key.push_back(plans[i].get());
-    }
-    if (user) SV_HIP(hipStreamSynchronize(user));
-    else SV_HIP(hipDeviceSynchronize());
-    // the last ensemble's graph is kept and replayed when the same states,
-    // plans and schedule come again
+    // plans (register tiles from |0..0>, one width for the ensemble) and the
+    // captured graph; the last ensemble's graph is kept and replayed when the
+    // same states, plans and schedule come again
     static EnsembleGraph *last = nullptr;   // kept for the process
-    if (!last || last->key != key) {
+    bool fallback = false;
+    auto prepare = [&](int vb) -> sv_status {
+        std::vector<std::shared_ptr<Plan>> plans(count);
+        std::vector<const void *> key;
+        key.push_back((const void *)(intptr_t)(persistent ? 1 : 0));
+        key.push_back((const void *)(intptr_t)vb);
+        for (int64_t i = 0; i < count; i++) {
+            PlanRequest rq{};
+            rq.n = sts[i]->n;
+            rq.dtype = dt;
+            rq.mode = SV_MODE_REGTILE;
+            rq.tile = vb;
+            rq.from_zero = true;
+            rq.force_zero = true;
+            SV_TRY(get_plan(sts[i], &cs[i], rq, &plans[i]));
+            for (const Op &op : plans[i]->ops)
+                if (op.type != OP_REGTILE || op.vbits != vb) {
+                    fallback = true;
+                    return SV_OK;
+                }
+            key.push_back(sts[i]->data);
+            key.push_back(plans[i].get());
+        }
+        if (last && last->key == key) return SV_OK;
         if (last) {
             last->release();
             delete last;
@@ -518,7 +465,48 @@ extern "C" sv_status sv_apply_batch(sv_state **sts, const sv_circuit *cs, int64_
         }
         g->key = key;
         last = g;
+        return SV_OK;
+    };
+    if (user) SV_HIP(hipStreamSynchronize(user));
+    else SV_HIP(hipDeviceSynchronize());
+    // width: given, or the fastest of 4..6 timed on this ensemble itself
+    // (once per list of instance sizes and schedule; the timing runs write
+    // the same outputs as the call)
+    static std::map<std::vector<int>, int> *width_of = new std::map<std::vector<int>, int>();
+    std::vector<int> shape;
+    shape.push_back(persistent ? 1 : 0);
+    for (int64_t i = 0; i < count; i++) shape.push_back(sts[i]->n);
+    int vb = 6;
+    if (opts && opts->mode == SV_MODE_REGTILE && opts->tile_qubits > 0) {
+        vb = std::min(6, std::max(3, opts->tile_qubits));
+    } else if (width_of->count(shape)) {
+        vb = (*width_of)[shape];
+    } else {
+        float best_ms = -1;
+        for (int w = 4; w <= 6; w++) {
+            SV_TRY(prepare(w));
+            if (fallback) return batch_graph_of_launches(sts, cs, count, opts, out);
+            hipEvent_t t0, t1;
+            SV_HIP(hipEventCreate(&t0));
+            SV_HIP(hipEventCreate(&t1));
+            (void)hipEventRecord(t0, last->stream);
+            hipError_t e = hipGraphLaunch(last->exec, last->stream);
+            (void)hipEventRecord(t1, last->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, t0, t1);
+            (void)hipEventDestroy(t0);
+            (void)hipEventDestroy(t1);
+            if (e != hipSuccess) return hip_fail(e, "ensemble width timing");
+            if (best_ms < 0 || ms < best_ms) {
+                best_ms = ms;
+                vb = w;
+            }
+        }
+        (*width_of)[shape] = vb;
     }
+    SV_TRY(prepare(vb));
+    if (fallback) return batch_graph_of_launches(sts, cs, count, opts, out);
     std::vector<double> host((size_t)count * 16);
     unsigned herr = 0;
     hipError_t e = hipGraphLaunch(last->exec, last->stream);

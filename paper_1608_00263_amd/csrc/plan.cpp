@@ -951,7 +951,7 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
         plan_per_gate(c, g, r2, plan);
     } else if (mode == SV_MODE_REGTILE) {
         fold_diagonals(&g, rq.n, false, true);
-        int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 5 : 4);
+        int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 6 : 5);
         vb = std::max(1, std::min(vb, rq.dtype == SV_C64 ? 6 : 5));
         vb = std::min(vb, rq.n - LANE_BITS);
         auto sweeps = regtile_sweeps(g, rq.n, vb, rq.dtype, rq.budget > 0 ? (double)rq.budget : -1.0);
