@@ -288,14 +288,18 @@ struct Sweep {
     std::vector<int> items;    // indices into the gate / block list, in order
 };
 
-// Greedy grouping of an ordered list of items into sweeps.  An item is
-// either "diagonal" (applicable in any sweep) or needs all of `need(i)` in
-// the sweep's qubit set, which holds qubits 0..5 plus at most `cap`
-// gathered ones.  Items are taken in list order; an item that cannot be
-// taken blocks its qubits for the rest of the sweep (a skipped diagonal
-// item blocks only non-diagonal items on its qubits, since diagonal items
-// commute).
-static std::vector<Sweep> group_sweeps(int nitems, int n, int cap,
+// Grouping of an ordered list of items into sweeps.  An item is either
+// "diagonal" (applicable in any sweep) or needs all of `qubits(i)` in the
+// sweep's qubit set, which holds qubits 0..5 plus at most `cap` gathered
+// ones.  Items are taken in list order; an item that cannot be taken blocks
+// its qubits for the rest of the sweep (a skipped diagonal item blocks only
+// non-diagonal items on its qubits, since diagonal items commute).
+//
+// Two groupings are built and the one with fewer sweeps kept: gathered sets
+// grown greedily in list order; and, per sweep, the best (by items taken)
+// of that greedy set and the `cap` qubits carrying the most non-diagonal
+// items among the next W pending items, for a few look-ahead windows W.
+static std::vector<Sweep> group_sweeps_once(bool lookahead, int nitems, int n, int cap,
                                        const std::function<bool(int)> &diag,
                                        const std::function<std::vector<int>(int)> &qubits,
                                        const std::function<double(int, const std::vector<char> &)> &cost =
@@ -304,19 +308,29 @@ static std::vector<Sweep> group_sweeps(int nitems, int n, int cap,
     std::vector<Sweep> out;
     std::vector<char> done(nitems, 0);
     int left = nitems;
+    std::vector<std::vector<int>> qs_of(nitems);
+    std::vector<char> is_diag(nitems);
+    for (int i = 0; i < nitems; i++) {
+        qs_of[i] = qubits(i);
+        is_diag[i] = diag(i) ? 1 : 0;
+    }
     std::vector<char> block_all(n), block_dense(n), in_tile(n);
-    while (left > 0) {
-        Sweep sw;
+    // one sweep from the current state; fixed != null: the gathered set is
+    // given, else it grows greedily
+    auto simulate = [&](const std::vector<char> *fixed, Sweep *sw) {
         std::fill(block_all.begin(), block_all.end(), 0);
         std::fill(block_dense.begin(), block_dense.end(), 0);
         std::fill(in_tile.begin(), in_tile.end(), 0);
         for (int q = 0; q < std::min(n, LANE_BITS); q++) in_tile[q] = 1;
         int ngather = 0;
+        if (fixed)
+            for (int q = LANE_BITS; q < n; q++)
+                if ((*fixed)[q]) { in_tile[q] = 1; sw->tile.push_back(q); ngather++; }
         double spent = 0;
         for (int i = 0; i < nitems; i++) {
             if (done[i]) continue;
-            std::vector<int> qs = qubits(i);
-            bool d = diag(i);
+            const std::vector<int> &qs = qs_of[i];
+            const bool d = is_diag[i];
             bool ok = true;
             for (int q : qs)
                 if (block_all[q] || (!d && block_dense[q])) ok = false;
@@ -324,10 +338,10 @@ static std::vector<Sweep> group_sweeps(int nitems, int n, int cap,
             if (ok && !d) {
                 for (int q : qs)
                     if (!in_tile[q]) need++;
-                if (ngather + need > cap) ok = false;
+                if (need && (fixed || ngather + need > cap)) ok = false;
             }
             // arithmetic budget of a sweep (the first item always fits)
-            if (ok && cost && !sw.items.empty()) {
+            if (ok && cost && !sw->items.empty()) {
                 std::vector<char> t2(in_tile);
                 for (int q : qs) t2[q] = 1;
                 double c = cost(i, d ? in_tile : t2);
@@ -337,22 +351,61 @@ static std::vector<Sweep> group_sweeps(int nitems, int n, int cap,
                 if (cost) spent += cost(i, in_tile);
                 if (!d)
                     for (int q : qs)
-                        if (!in_tile[q]) { in_tile[q] = 1; sw.tile.push_back(q); ngather++; }
-            }
-            if (ok) {
-                sw.items.push_back(i);
-                done[i] = 1;
-                left--;
+                        if (!in_tile[q]) { in_tile[q] = 1; sw->tile.push_back(q); ngather++; }
+                sw->items.push_back(i);
             } else if (d) {
                 for (int q : qs) block_dense[q] = 1;
             } else {
                 for (int q : qs) block_all[q] = 1;
             }
         }
-        std::sort(sw.tile.begin(), sw.tile.end());
-        out.push_back(sw);
+        std::sort(sw->tile.begin(), sw->tile.end());
+    };
+    while (left > 0) {
+        Sweep best;
+        simulate(nullptr, &best);
+        for (int W : {24, 48, 96, 192}) {
+            if (!lookahead) break;
+            std::vector<int> count(n, 0), first(n, nitems);
+            int seen = 0;
+            for (int i = 0; i < nitems && seen < W; i++) {
+                if (done[i]) continue;
+                seen++;
+                if (is_diag[i]) continue;
+                for (int q : qs_of[i])
+                    if (q >= LANE_BITS) {
+                        count[q]++;
+                        first[q] = std::min(first[q], i);
+                    }
+            }
+            std::vector<int> cand;
+            for (int q = LANE_BITS; q < n; q++)
+                if (count[q] > 0) cand.push_back(q);
+            std::sort(cand.begin(), cand.end(), [&](int a, int b) {
+                return count[a] != count[b] ? count[a] > count[b] : first[a] < first[b];
+            });
+            if ((int)cand.size() > cap) cand.resize(cap);
+            std::vector<char> fixed(n, 0);
+            for (int q : cand) fixed[q] = 1;
+            Sweep sw;
+            simulate(&fixed, &sw);
+            if (sw.items.size() > best.items.size()) best = sw;
+        }
+        for (int i : best.items) done[i] = 1;
+        left -= (int)best.items.size();
+        out.push_back(best);
     }
     return out;
+}
+
+static std::vector<Sweep> group_sweeps(int nitems, int n, int cap, const std::function<bool(int)> &diag,
+                                       const std::function<std::vector<int>(int)> &qubits,
+                                       const std::function<double(int, const std::vector<char> &)> &cost =
+                                           nullptr,
+                                       double budget = 0) {
+    std::vector<Sweep> a = group_sweeps_once(false, nitems, n, cap, diag, qubits, cost, budget);
+    std::vector<Sweep> b = group_sweeps_once(true, nitems, n, cap, diag, qubits, cost, budget);
+    return b.size() < a.size() ? b : a;
 }
 
 static uint64_t bit64(int q) { return (uint64_t)1 << q; }
