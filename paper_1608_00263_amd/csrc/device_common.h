@@ -376,18 +376,22 @@ __device__ __forceinline__ void regtile_apply(cplx<T> *__restrict__ psi, const u
                                               uint64_t tile, int lane) {
     constexpr int NR = 1 << VB;
     const cptr<RTHeader> h = (cptr<RTHeader>)prog;
-    int rq[VB];
-#pragma unroll
-    for (int i = 0; i < VB; i++) rq[i] = h->rq[i];
-    uint64_t base = tile << LANE_BITS;
-#pragma unroll
-    for (int i = 0; i < VB; i++) base = insert_zero(base, rq[i]);
     uint64_t bq[VB];
 #pragma unroll
-    for (int i = 0; i < VB; i++) bq[i] = 1ull << rq[i];
+    for (int i = 0; i < VB; i++) bq[i] = 1ull << h->rq[i];
+    // tile base: the tile index with zeros inserted at the tile's qubits
+    // above 3 (lane qubits and register qubits), in ascending order
+    uint64_t base = tile << 4;
+#pragma unroll
+    for (int i = 0; i < VB + 2; i++) base = insert_zero(base, h->tq[i]);
+    // lane bits 0..3 are qubits 0..3; lane bits 4 and 5 are qubits lq[0],
+    // lq[1].  With lq = (4, 5) a row is 64 contiguous amplitudes: uniform row
+    // pointer (scalar registers) + lane index, one address register per lane.
+    const int l4 = h->lq[0], l5 = h->lq[1];
+    const bool rows = (l4 == 4) & (l5 == 5);
+    const uint64_t loff = (uint64_t)(lane & 15) | ((uint64_t)((lane >> 4) & 1) << l4) |
+                          ((uint64_t)((lane >> 5) & 1) << l5);
 
-    // uniform row pointer (scalar registers) + lane index: one address
-    // register per lane instead of one 64-bit address per amplitude
     cplx<T> a[NR];
     const int gen_n = h->gen_n;
     if (gen_n > 0) {
@@ -396,9 +400,12 @@ __device__ __forceinline__ void regtile_apply(cplx<T> *__restrict__ psi, const u
         if (gen_n & 1) v *= (T)0.70710678118654752440;
 #pragma unroll
         for (int r = 0; r < NR; r++) { a[r].re = v; a[r].im = (T)0; }
-    } else {
+    } else if (rows) {
 #pragma unroll
         for (int r = 0; r < NR; r++) a[r] = gload<T>(uniform_ptr(psi + (base + reg_offset<VB>(bq, r))) + lane);
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) a[r] = gload<T>(uniform_ptr(psi + (base + reg_offset<VB>(bq, r))) + loff);
     }
 
     const cptr<RTOp> ops = (cptr<RTOp>)(prog + h->op_off);
@@ -466,8 +473,13 @@ __device__ __forceinline__ void regtile_apply(cplx<T> *__restrict__ psi, const u
             a[r].im *= f;
         }
     }
+    if (rows) {
 #pragma unroll
-    for (int r = 0; r < NR; r++) gstore<T>(uniform_ptr(psi + (base + reg_offset<VB>(bq, r))) + lane, a[r]);
+        for (int r = 0; r < NR; r++) gstore<T>(uniform_ptr(psi + (base + reg_offset<VB>(bq, r))) + lane, a[r]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) gstore<T>(uniform_ptr(psi + (base + reg_offset<VB>(bq, r))) + loff, a[r]);
+    }
 }
 
 

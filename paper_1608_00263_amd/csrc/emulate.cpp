@@ -29,12 +29,16 @@ static void emulate_regtile(const Plan &plan, const Op &op, int n, cx *psi) {
     const uint64_t ntiles = (1ull << n) >> (LANE_BITS + vb);
     std::vector<uint64_t> roff(nr, 0);
     for (int r = 1; r < nr; r++) roff[r] = roff[r & (r - 1)] | (1ull << h->rq[__builtin_ctz(r)]);
+    // lane l: bits 0..3 are qubits 0..3, bits 4 and 5 qubits lq[0], lq[1]
+    std::vector<uint64_t> loff(64);
+    for (int l = 0; l < 64; l++)
+        loff[l] = (uint64_t)(l & 15) | ((uint64_t)((l >> 4) & 1) << h->lq[0]) | ((uint64_t)((l >> 5) & 1) << h->lq[1]);
     std::vector<cx> a(64 * nr);
     const bool f32 = plan.dtype == SV_C64;
     auto rnd = [&](cx v) { return f32 ? cx((float)v.real(), (float)v.imag()) : v; };
     for (uint64_t tile = 0; tile < ntiles; tile++) {
-        uint64_t base = tile << LANE_BITS;
-        for (int i = 0; i < vb; i++) base = ins0(base, h->rq[i]);
+        uint64_t base = tile << 4;
+        for (int i = 0; i < vb + 2; i++) base = ins0(base, h->tq[i]);
         for (int l = 0; l < 64; l++)
             for (int r = 0; r < nr; r++) {
                 if (h->gen_n > 0) {
@@ -42,7 +46,7 @@ static void emulate_regtile(const Plan &plan, const Op &op, int n, cx *psi) {
                     if (h->gen_n & 1) v /= std::sqrt(2.0);
                     a[l * nr + r] = f32 ? (double)(float)v : v;
                 } else {
-                    a[l * nr + r] = psi[base + roff[r] + l];
+                    a[l * nr + r] = psi[base + roff[r] + loff[l]];
                 }
             }
         for (int o = 0; o < h->nops; o++) {
@@ -103,7 +107,7 @@ static void emulate_regtile(const Plan &plan, const Op &op, int n, cx *psi) {
         }
         const double sc = std::ldexp(1.0, h->sexp) * (h->shalf ? 1.0 / std::sqrt(2.0) : 1.0) * h->fscale;
         for (int l = 0; l < 64; l++)
-            for (int r = 0; r < nr; r++) psi[base + roff[r] + l] = a[l * nr + r] * sc;
+            for (int r = 0; r < nr; r++) psi[base + roff[r] + loff[l]] = a[l * nr + r] * sc;
     }
 }
 
@@ -299,6 +303,7 @@ extern "C" sv_status sv_host_plan_describe(const sv_circuit *c, sv_dtype dt, con
             }
             std::string rq;
             for (int j = 0; j < h->vbits; j++) rq += (j ? "," : "") + std::to_string(h->rq[j]);
+            rq += "] lanes=[" + std::to_string(h->lq[0]) + "," + std::to_string(h->lq[1]);
             std::string fs;
             static const char *fname[12] = {"gen", "h", "sx", "sy", "sxdg", "sydg", "phase", "rx", "ry", "real",
                                             "trx", "try"};

@@ -122,7 +122,7 @@ struct DiagTerm {           // 48 bytes
     uint64_t pad2;
 };
 
-struct RTHeader {           // 80 bytes
+struct RTHeader {           // 112 bytes
     int32_t nops;
     int32_t vbits;
     int32_t rq[8];          // register qubits, ascending
@@ -135,7 +135,10 @@ struct RTHeader {           // 80 bytes
                             // 2^{-gen_n/2} of gen_n qubits (Hadamard layer)
     double fscale;          // store: amplitudes also scaled by fscale (the
                             // product of the cosines of the F_TRX/F_TRY ops)
-    int32_t pad[2];
+    int32_t lq[2];          // qubits on lane bits 4 and 5 (lane bits 0..3 are
+                            // qubits 0..3); 4 and 5 give contiguous rows
+    int32_t tq[8];          // the tile's qubits above 3 (lane qubits and
+                            // register qubits), ascending: vbits + 2 entries
 };
 
 // LDS-tile ops

@@ -290,8 +290,8 @@ struct Sweep {
 
 // Grouping of an ordered list of items into sweeps.  An item is either
 // "diagonal" (applicable in any sweep) or needs all of `qubits(i)` in the
-// sweep's qubit set, which holds qubits 0..5 plus at most `cap` gathered
-// ones.  Items are taken in list order; an item that cannot be taken blocks
+// sweep's qubit set, which holds qubits 0..nfixed-1 plus at most `cap`
+// gathered ones.  Items are taken in list order; an item that cannot be taken blocks
 // its qubits for the rest of the sweep (a skipped diagonal item blocks only
 // non-diagonal items on its qubits, since diagonal items commute).
 //
@@ -299,12 +299,11 @@ struct Sweep {
 // grown greedily in list order; and, per sweep, the best (by items taken)
 // of that greedy set and the `cap` qubits carrying the most non-diagonal
 // items among the next W pending items, for a few look-ahead windows W.
-static std::vector<Sweep> group_sweeps_once(bool lookahead, int nitems, int n, int cap,
-                                       const std::function<bool(int)> &diag,
-                                       const std::function<std::vector<int>(int)> &qubits,
-                                       const std::function<double(int, const std::vector<char> &)> &cost =
-                                           nullptr,
-                                       double budget = 0) {
+static std::vector<Sweep> group_sweeps_once(bool lookahead, int nfixed, int nitems, int n, int cap,
+                                            const std::function<bool(int)> &diag,
+                                            const std::function<std::vector<int>(int)> &qubits,
+                                            const std::function<double(int, const std::vector<char> &)> &cost,
+                                            double budget) {
     std::vector<Sweep> out;
     std::vector<char> done(nitems, 0);
     int left = nitems;
@@ -321,10 +320,10 @@ static std::vector<Sweep> group_sweeps_once(bool lookahead, int nitems, int n, i
         std::fill(block_all.begin(), block_all.end(), 0);
         std::fill(block_dense.begin(), block_dense.end(), 0);
         std::fill(in_tile.begin(), in_tile.end(), 0);
-        for (int q = 0; q < std::min(n, LANE_BITS); q++) in_tile[q] = 1;
+        for (int q = 0; q < std::min(n, nfixed); q++) in_tile[q] = 1;
         int ngather = 0;
         if (fixed)
-            for (int q = LANE_BITS; q < n; q++)
+            for (int q = nfixed; q < n; q++)
                 if ((*fixed)[q]) { in_tile[q] = 1; sw->tile.push_back(q); ngather++; }
         double spent = 0;
         for (int i = 0; i < nitems; i++) {
@@ -373,13 +372,13 @@ static std::vector<Sweep> group_sweeps_once(bool lookahead, int nitems, int n, i
                 seen++;
                 if (is_diag[i]) continue;
                 for (int q : qs_of[i])
-                    if (q >= LANE_BITS) {
+                    if (q >= nfixed) {
                         count[q]++;
                         first[q] = std::min(first[q], i);
                     }
             }
             std::vector<int> cand;
-            for (int q = LANE_BITS; q < n; q++)
+            for (int q = nfixed; q < n; q++)
                 if (count[q] > 0) cand.push_back(q);
             std::sort(cand.begin(), cand.end(), [&](int a, int b) {
                 return count[a] != count[b] ? count[a] > count[b] : first[a] < first[b];
@@ -398,13 +397,14 @@ static std::vector<Sweep> group_sweeps_once(bool lookahead, int nitems, int n, i
     return out;
 }
 
+// nfixed: qubits 0..nfixed-1 are always in the sweep's set (the lanes).
 static std::vector<Sweep> group_sweeps(int nitems, int n, int cap, const std::function<bool(int)> &diag,
                                        const std::function<std::vector<int>(int)> &qubits,
                                        const std::function<double(int, const std::vector<char> &)> &cost =
                                            nullptr,
-                                       double budget = 0) {
-    std::vector<Sweep> a = group_sweeps_once(false, nitems, n, cap, diag, qubits, cost, budget);
-    std::vector<Sweep> b = group_sweeps_once(true, nitems, n, cap, diag, qubits, cost, budget);
+                                       double budget = 0, int nfixed = LANE_BITS) {
+    std::vector<Sweep> a = group_sweeps_once(false, nfixed, nitems, n, cap, diag, qubits, cost, budget);
+    std::vector<Sweep> b = group_sweeps_once(true, nfixed, nitems, n, cap, diag, qubits, cost, budget);
     return b.size() < a.size() ? b : a;
 }
 
@@ -494,14 +494,55 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
     RTProgram P;
     RTHeader &h = P.h;
     h.vbits = vbits;
-    // unused register slots are filled with further qubits so that every
-    // tile covers 2^(6+vbits) distinct amplitudes
-    std::vector<int> rq(sw.tile.begin(), sw.tile.end());
-    for (int q = LANE_BITS; (int)rq.size() < vbits && q < n; q++)
-        if (std::find(rq.begin(), rq.end(), q) == rq.end()) rq.push_back(q);
+    // Lane bits 0..3 are qubits 0..3.  Lane bits 4 and 5 take qubits 4 and 5
+    // when the sweep has them (contiguous 512-byte rows), else the gathered
+    // qubits with the fewest dense gates in the sweep (cross-lane gates cost
+    // more than register gates).  The other gathered qubits go to registers;
+    // unused slots are filled with further qubits so that every tile covers
+    // 2^(6+vbits) distinct amplitudes.
+    std::vector<int> G(sw.tile.begin(), sw.tile.end());
+    for (int q = 4; q < std::min(n, LANE_BITS); q++)
+        if (std::find(G.begin(), G.end(), q) == G.end() && (int)G.size() < vbits + 2) G.push_back(q);
+    std::vector<int> dense(64, 0);
+    for (int idx : sw.items)
+        if (g[idx].kind == SG_DENSE) dense[g[idx].q0]++;
+    std::vector<int> lq, rq;
+    for (int q : {4, 5})
+        if (std::find(G.begin(), G.end(), q) != G.end()) lq.push_back(q);
+    std::vector<int> rest;
+    for (int q : G)
+        if (std::find(lq.begin(), lq.end(), q) == lq.end()) rest.push_back(q);
+    std::sort(rest.begin(), rest.end(), [&](int a, int b) { return dense[a] != dense[b] ? dense[a] < dense[b] : a < b; });
+    // keep the gathered set's register share within vbits
+    size_t take_lanes = rest.size() > (size_t)vbits ? rest.size() - (size_t)vbits : 0;
+    for (size_t i = 0; i < rest.size(); i++) {
+        if (lq.size() < 2 && (i < take_lanes || (int)(rest.size() - i) > vbits)) lq.push_back(rest[i]);
+        else rq.push_back(rest[i]);
+    }
+    auto used = [&](int q) {
+        return q < 4 || std::find(lq.begin(), lq.end(), q) != lq.end() ||
+               std::find(rq.begin(), rq.end(), q) != rq.end();
+    };
+    for (int q = 4; lq.size() < 2 && q < n; q++)
+        if (!used(q)) lq.push_back(q);
+    for (int q = 4; (int)rq.size() < vbits && q < n; q++)
+        if (!used(q)) rq.push_back(q);
+    std::sort(lq.begin(), lq.end());
     std::sort(rq.begin(), rq.end());
-    std::vector<int> slot(64, -1);
-    for (int i = 0; i < 8; i++) h.rq[i] = i < (int)rq.size() ? rq[i] : -1;
+    std::vector<int> slot(64, -1), lane_of(64, -1);
+    for (int q = 0; q < 4; q++) lane_of[q] = q;
+    lane_of[lq[0]] = 4;
+    lane_of[lq[1]] = 5;
+    h.lq[0] = lq[0];
+    h.lq[1] = lq[1];
+    std::vector<int> tq(rq);
+    tq.push_back(lq[0]);
+    tq.push_back(lq[1]);
+    std::sort(tq.begin(), tq.end());
+    for (int i = 0; i < 8; i++) {
+        h.rq[i] = i < (int)rq.size() ? rq[i] : -1;
+        h.tq[i] = i < (int)tq.size() ? tq[i] : -1;
+    }
     for (size_t i = 0; i < rq.size(); i++) slot[rq[i]] = (int)i;
     std::vector<RTOp> &ops = P.ops;
     std::vector<DiagTerm> &terms = P.terms;
@@ -510,7 +551,7 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
         uint32_t rbits = 0;
         for (int q = 0; q < 64; q++) {
             if (!(mask & bit64(q))) continue;
-            if (q < LANE_BITS) t.lanemask |= 1u << q;
+            if (lane_of[q] >= 0) t.lanemask |= 1u << lane_of[q];
             else if (slot[q] >= 0) rbits |= 1u << slot[q];
             else t.outside |= bit64(q);
         }
@@ -521,10 +562,10 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
     int nc = 0;
     for (int idx : batch_diagonals(g, sw.items)) {
         const SGate &s = g[idx];
-        const bool in_tile = s.q0 < LANE_BITS || slot[s.q0] >= 0;
+        const bool in_tile = lane_of[s.q0] >= 0 || slot[s.q0] >= 0;
         if (s.kind == SG_DENSE || (s.kind == SG_DIAG1 && in_tile)) {
             RTOp o{};
-            if (s.q0 < LANE_BITS) { o.kind = RT_LANE; o.a = s.q0; }
+            if (lane_of[s.q0] >= 0) { o.kind = RT_LANE; o.a = lane_of[s.q0]; }
             else { o.kind = RT_REG; o.a = slot[s.q0]; }
             put_mat(o.u, s.u);
             o.slot = s.slot;
@@ -933,13 +974,16 @@ static void plan_per_gate(const sv_circuit *c, const std::vector<SGate> &g, cons
 // add-only and rotation (tangent) forms 2 on a register qubit and 5 on a
 // lane qubit (cross-lane moves), general 2x2 gates 8 and 11, phases 2
 // (register) or 4, and 1 per CZ sign flip.
+// flex: lane bits 4 and 5 may take any qubit (the sweep gathers vb + 2
+// qubits above 3) instead of qubits 4 and 5.
 static std::vector<Sweep> regtile_sweeps(const std::vector<SGate> &g, int n, int vb, int dtype,
-                                         double budget = -1) {
+                                         double budget = -1, bool flex = false) {
     if (budget < 0) budget = dtype == SV_C64 ? 110.0 : 220.0;
+    const int nfixed = flex ? 4 : LANE_BITS;
     auto cost = [&](int i, const std::vector<char> &in_tile) -> double {
         const SGate &s = g[i];
         if (s.kind == SG_CZ) return 1.0;
-        const bool lane = s.q0 < LANE_BITS;
+        const bool lane = s.q0 < nfixed;
         const bool reg = !lane && in_tile[s.q0];
         if (s.kind == SG_DIAG1) return reg ? 2.0 : 4.0;
         if (form_scaled(s.form) || s.form == F_RX || s.form == F_RY) return lane ? 5.0 : 2.0;
@@ -947,13 +991,13 @@ static std::vector<Sweep> regtile_sweeps(const std::vector<SGate> &g, int n, int
         return lane ? 7.0 : 4.0;   // real forms
     };
     return group_sweeps(
-        (int)g.size(), n, vb, [&](int i) { return g[i].kind != SG_DENSE; },
+        (int)g.size(), n, vb + (LANE_BITS - nfixed), [&](int i) { return g[i].kind != SG_DENSE; },
         [&](int i) {
             std::vector<int> q = {g[i].q0};
             if (g[i].kind == SG_CZ) q.push_back(g[i].q1);
             return q;
         },
-        cost, budget);
+        cost, budget, nfixed);
 }
 
 std::string plan_key(const sv_circuit *c, const PlanRequest &rq) {
@@ -1007,7 +1051,7 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
         int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 6 : 5);
         vb = std::max(1, std::min(vb, rq.dtype == SV_C64 ? 6 : 5));
         vb = std::min(vb, rq.n - LANE_BITS);
-        auto sweeps = regtile_sweeps(g, rq.n, vb, rq.dtype, rq.budget > 0 ? (double)rq.budget : -1.0);
+        auto sweeps = regtile_sweeps(g, rq.n, vb, rq.dtype, rq.budget > 0 ? (double)rq.budget : -1.0, true);
         std::vector<std::pair<size_t, int>> scales;
         for (const Sweep &sw : sweeps) emit_regtile(g, sw, vb, rq.n, rq.dtype, plan, &scales);
         assign_scales(plan, scales);
