@@ -122,7 +122,7 @@ typedef struct {
     int32_t flags;        /* SV_FLAG_* bits                                   */
     int32_t sweep_budget; /* REGTILE: vector instructions per amplitude
                              register one sweep may spend on gates before a
-                             new sweep starts (0 = default, 110 complex64,
+                             new sweep starts (0 = default, 250 complex64,
                              220 complex128; 20..2000)                       */
 } sv_opts;
 
