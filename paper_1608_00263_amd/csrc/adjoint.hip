@@ -234,20 +234,31 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t tile = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
     if (tile >= ntiles) return;
-    int rq[VB];
-#pragma unroll
-    for (int i = 0; i < VB; i++) rq[i] = h->rq[i];
-    uint64_t base = tile << LANE_BITS;
-#pragma unroll
-    for (int i = 0; i < VB; i++) base = insert_zero(base, rq[i]);
     uint64_t bq[VB];
 #pragma unroll
-    for (int i = 0; i < VB; i++) bq[i] = 1ull << rq[i];
-    cplx<T> phi[NR], mu[NR];
+    for (int i = 0; i < VB; i++) bq[i] = 1ull << h->rq[i];
+    // the tile layout of the forward register tiles: zeros inserted at the
+    // tile's qubits above 3; lane bits 4 and 5 are qubits lq[0], lq[1]
+    uint64_t base = tile << 4;
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        phi[r] = gload<T>(uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r))) + lane);
-        mu[r] = gload<T>(uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r))) + lane);
+    for (int i = 0; i < VB + 2; i++) base = insert_zero(base, h->tq[i]);
+    const int l4 = h->lq[0], l5 = h->lq[1];
+    const bool rows = (l4 == 4) & (l5 == 5);
+    const uint64_t loff = (uint64_t)(lane & 15) | ((uint64_t)((lane >> 4) & 1) << l4) |
+                          ((uint64_t)((lane >> 5) & 1) << l5);
+    cplx<T> phi[NR], mu[NR];
+    if (rows) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            phi[r] = gload<T>(uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r))) + lane);
+            mu[r] = gload<T>(uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r))) + lane);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            phi[r] = gload<T>(uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r))) + loff);
+            mu[r] = gload<T>(uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r))) + loff);
+        }
     }
     const cptr<RTOp> ops = (cptr<RTOp>)(prog + h->op_off);
     const cptr<DiagTerm> terms = (cptr<DiagTerm>)(prog + h->term_off);
@@ -339,10 +350,18 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
             mu[r].re *= f; mu[r].im *= f;
         }
     }
+    if (rows) {
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        gstore<T>(uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r))) + lane, phi[r]);
-        gstore<T>(uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r))) + lane, mu[r]);
+        for (int r = 0; r < NR; r++) {
+            gstore<T>(uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r))) + lane, phi[r]);
+            gstore<T>(uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r))) + lane, mu[r]);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            gstore<T>(uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r))) + loff, phi[r]);
+            gstore<T>(uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r))) + loff, mu[r]);
+        }
     }
 }
 
@@ -519,6 +538,8 @@ extern "C" sv_status sv_backward(sv_state *st, const sv_circuit *c, const sv_opt
     rq.dtype = st->dt;
     rq.mode = SV_MODE_REGTILE;
     rq.tile = opts ? opts->tile_qubits : 0;
+    rq.budget = opts ? opts->sweep_budget : 0;
+    if (rq.budget != 0 && (rq.budget < 20 || rq.budget > 2000)) return fail(SV_EINVAL, "sweep_budget must be 0 or 20..2000");
     rq.from_zero = true;
     rq.k_max = 1000 + checkpoint_c;   // distinct cache key per checkpoint interval
     std::string key = "adj:" + plan_key(c, rq);

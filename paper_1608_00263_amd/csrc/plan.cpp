@@ -1163,7 +1163,8 @@ sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int che
     for (int k = 0; k < nseg; k++) {
         // the reverse sweeps carry two states and the gradient shares: the
         // memory-time budget, not the longer forward one
-        for (const Sweep &sw : regtile_sweeps(segs[k], rq.n, vb, rq.dtype, rq.dtype == SV_C64 ? 110.0 : 220.0)) {
+        const double budget = rq.budget > 0 ? (double)rq.budget : (rq.dtype == SV_C64 ? 110.0 : 220.0);
+        for (const Sweep &sw : regtile_sweeps(segs[k], rq.n, vb, rq.dtype, budget, true)) {
             progs[k].push_back(build_regtile(segs[k], sw, vb, rq.n));
             push_regtile(progs[k].back(), rq.n, rq.dtype, OP_REGTILE, &plan->ops, plan);
         }

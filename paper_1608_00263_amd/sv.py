@@ -267,12 +267,12 @@ class State:
         return ce.value, dh.value, z.value
 
     def backward(self, circ, samples: np.ndarray, checkpoint_c: int = 0, mode="auto", k_max=0,
-                 tile=0, state_ready=False):
+                 tile=0, state_ready=False, budget=0):
         """Loss and adjoint gradient; state_ready=True reuses the output state
         the handle holds (left by apply() of the same circuit) instead of
         recomputing it."""
         a = CircuitArgs(circ)
-        o = make_opts(mode, k_max, tile, flags=FLAG_STATE_READY if state_ready else 0)
+        o = make_opts(mode, k_max, tile, flags=FLAG_STATE_READY if state_ready else 0, budget=budget)
         x = np.ascontiguousarray(samples, dtype=np.uint64)
         grad = np.zeros(max(circ.nparams, 1))
         loss = ctypes.c_double()
