@@ -313,6 +313,34 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
                     mu[r].re = -mu[r].re; mu[r].im = -mu[r].im;
                 }
             }
+        } else if (kind == RT_PHASE && slot < 0) {
+            // a group of phase terms sharing one register set (no gradient):
+            // the per-lane product of the matching phases, applied once
+            const int nt = ops[o].nterms;
+            const uint64_t rs = terms[arg].regset;
+            cplx<T> f;
+            f.re = (T)1;
+            f.im = (T)0;
+            bool any = false;
+            for (int t = arg; t < arg + nt; t++) {
+                const uint64_t out = terms[t].outside;
+                if ((base & out) != out) continue;
+                any = true;
+                const uint32_t lm = terms[t].lanemask;
+                cplx<T> v;
+                v.re = (T)terms[t].val[0];
+                v.im = (T)terms[t].val[1];
+                const cplx<T> fv = cmul(v, f);
+                if (((uint32_t)lane & lm) == lm) f = fv;
+            }
+            if (any) {
+#pragma unroll
+                for (int r = 0; r < NR; r++)
+                    if ((rs >> r) & 1) {
+                        phi[r] = cmul(f, phi[r]);
+                        mu[r] = cmul(f, mu[r]);
+                    }
+            }
         } else if (kind == RT_PHASE) {
             const uint64_t out = terms[arg].outside;
             const bool tile_on = (base & out) == out;
@@ -408,19 +436,38 @@ __global__ __launch_bounds__(256) void k_grad_partial(const double *__restrict__
     }
 }
 
-__global__ void k_grad_final(const double *__restrict__ part, uint64_t nchunks, int nslots,
-                             double *__restrict__ out) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nslots) return;
+// One workgroup of 64 threads per slot: 64 segments of the chunk partials
+// are summed in parallel (Neumaier), then the segment sums and
+// compensations are combined in segment order by the first thread.
+__global__ __launch_bounds__(64) void k_grad_final(const double *__restrict__ part, uint64_t nchunks,
+                                                   int nslots, double *__restrict__ out) {
+    __shared__ double ss[64], cc[64];
+    const int s = blockIdx.x;
+    const uint64_t per = (nchunks + 63) / 64;
+    const uint64_t b0 = threadIdx.x * per, b1 = b0 + per < nchunks ? b0 + per : nchunks;
     double sum = 0, c = 0;
-    for (uint64_t b = 0; b < nchunks; b++) {
+    for (uint64_t b = b0; b < b1; b++) {
         const double x = part[b * (uint64_t)nslots + s];
         const double u = sum + x;
         if (fabs(sum) >= fabs(x)) c += (sum - u) + x;
         else c += (x - u) + sum;
         sum = u;
     }
-    out[s] = -2.0 * (sum + c);
+    ss[threadIdx.x] = sum;
+    cc[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double S = 0, Cc = 0;
+        for (int g = 0; g < 64; g++) {
+            const double x = ss[g];
+            const double u = S + x;
+            if (fabs(S) >= fabs(x)) Cc += (S - u) + x;
+            else Cc += (x - u) + S;
+            S = u;
+            Cc += cc[g];
+        }
+        out[s] = -2.0 * (S + Cc);
+    }
 }
 
 static unsigned ggrid(uint64_t items) {
@@ -508,7 +555,7 @@ static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *
         double *gchunk = gsum + nslots;
         hipLaunchKernelGGL(k_grad_partial, dim3((unsigned)nchunks), dim3(256), 0, s, gpart, ntiles, nslots,
                            gchunk);
-        hipLaunchKernelGGL(k_grad_final, dim3((nslots + 255) / 256), dim3(256), 0, s, gchunk, nchunks, nslots,
+        hipLaunchKernelGGL(k_grad_final, dim3(nslots), dim3(64), 0, s, gchunk, nchunks, nslots,
                            gsum);
         SV_HIP(hipGetLastError());
         SV_HIP(hipMemcpyAsync(slots.data(), gsum, nslots * 8, hipMemcpyDeviceToHost, s));

@@ -433,16 +433,30 @@ __device__ __forceinline__ void regtile_apply(cplx<T> *__restrict__ psi, const u
                 if ((par >> r) & 1) { a[r].re = -a[r].re; a[r].im = -a[r].im; }
             }
         } else if (kind == RT_PHASE) {
-            const uint64_t out = terms[arg].outside;
-            if ((base & out) == out) {
-                const uint32_t lm = terms[arg].lanemask;
-                const uint64_t rs = ((uint32_t)lane & lm) == lm ? terms[arg].regset : 0ull;
+            // a group of phase terms sharing one register set: the product
+            // of the phases whose lane and outside bits match, per lane,
+            // then one multiplication of the group's registers
+            const int nt = ops[o].nterms;
+            const uint64_t rs = terms[arg].regset;
+            cplx<T> f;
+            f.re = (T)1;
+            f.im = (T)0;
+            bool any = false;
+            for (int t = arg; t < arg + nt; t++) {
+                const uint64_t out = terms[t].outside;
+                if ((base & out) != out) continue;
+                any = true;
+                const uint32_t lm = terms[t].lanemask;
                 cplx<T> v;
-                v.re = (T)terms[arg].val[0];
-                v.im = (T)terms[arg].val[1];
+                v.re = (T)terms[t].val[0];
+                v.im = (T)terms[t].val[1];
+                const cplx<T> fv = cmul(v, f);
+                if (((uint32_t)lane & lm) == lm) f = fv;
+            }
+            if (any) {
 #pragma unroll
                 for (int r = 0; r < NR; r++)
-                    if ((rs >> r) & 1) a[r] = cmul(v, a[r]);
+                    if ((rs >> r) & 1) a[r] = cmul(f, a[r]);
             }
         }
     }

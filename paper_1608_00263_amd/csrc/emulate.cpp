@@ -85,7 +85,7 @@ static void emulate_regtile(const Plan &plan, const Op &op, int n, cx *psi) {
                     }
                 }
             } else if (p.kind == RT_SIGNS || p.kind == RT_PHASE) {
-                int t0 = p.a, t1 = p.a + (p.kind == RT_SIGNS ? p.nterms : 1);
+                int t0 = p.a, t1 = p.a + p.nterms;
                 for (int l = 0; l < 64; l++) {
                     uint64_t par = 0;
                     for (int t = t0; t < t1; t++) {

@@ -638,6 +638,59 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
             }
         }
     }
+    // Runs of consecutive phase terms without gradient slots commute: group
+    // them by register set, one op per group (the kernel multiplies the
+    // group's registers once by a per-lane product of the term phases).
+    {
+        std::vector<RTOp> nops;
+        std::vector<double> nopc;
+        std::vector<DiagTerm> nterms;
+        for (size_t i = 0; i < ops.size();) {
+            const RTOp &o = ops[i];
+            if (o.kind == RT_SIGNS) {
+                RTOp c = o;
+                c.a = (int)nterms.size();
+                for (int t = 0; t < o.nterms; t++) nterms.push_back(terms[o.a + t]);
+                nops.push_back(c);
+                nopc.push_back(P.opc[i]);
+                i++;
+                continue;
+            }
+            if (o.kind != RT_PHASE || o.slot >= 0) {
+                RTOp c = o;
+                if (o.kind == RT_PHASE) {
+                    c.a = (int)nterms.size();
+                    nterms.push_back(terms[o.a]);
+                }
+                nops.push_back(c);
+                nopc.push_back(P.opc[i]);
+                i++;
+                continue;
+            }
+            size_t j = i;
+            while (j < ops.size() && ops[j].kind == RT_PHASE && ops[j].slot < 0) j++;
+            std::vector<char> used(j - i, 0);
+            for (size_t u = i; u < j; u++) {
+                if (used[u - i]) continue;
+                const uint64_t rs = terms[ops[u].a].regset;
+                RTOp c = ops[u];
+                c.a = (int)nterms.size();
+                c.nterms = 0;
+                for (size_t w = u; w < j; w++)
+                    if (!used[w - i] && terms[ops[w].a].regset == rs) {
+                        used[w - i] = 1;
+                        nterms.push_back(terms[ops[w].a]);
+                        c.nterms++;
+                    }
+                nops.push_back(c);
+                nopc.push_back(1.0);
+            }
+            i = j;
+        }
+        ops.swap(nops);
+        P.opc.swap(nopc);
+        terms.swap(nterms);
+    }
     if (ncheap) *ncheap = nc;
     return P;
 }
