@@ -369,6 +369,55 @@ __device__ __forceinline__ Mat2<T> load_mat(PD u) {
 }
 
 
+// One register-tile op: kind, argument, term count, form and its 2x2 matrix.
+template <typename T, int NR>
+__device__ __forceinline__ void regtile_op(cplx<T> (&a)[NR], int kind, int arg, int nt, int form, const Mat2<T> &u,
+                                           const cptr<DiagTerm> terms, uint64_t base, int lane) {
+    if (kind == RT_REG) {
+        reg_gate_dispatch<T, NR>(a, u, arg, form);
+    } else if (kind == RT_LANE) {
+        lane_gate_dispatch<T, NR>(a, u, arg, lane, form);
+    } else if (kind == RT_SIGNS) {
+        uint64_t par = 0;
+        for (int t = arg; t < arg + nt; t++) {
+            const uint64_t out = terms[t].outside;
+            if ((base & out) != out) continue;
+            const uint32_t lm = terms[t].lanemask;
+            const uint64_t rs = terms[t].regset;
+            par ^= ((uint32_t)lane & lm) == lm ? rs : 0ull;
+        }
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if ((par >> r) & 1) { a[r].re = -a[r].re; a[r].im = -a[r].im; }
+        }
+    } else if (kind == RT_PHASE) {
+        // a group of phase terms sharing one register set: the product
+        // of the phases whose lane and outside bits match, per lane,
+        // then one multiplication of the group's registers
+        const uint64_t rs = terms[arg].regset;
+        cplx<T> f;
+        f.re = (T)1;
+        f.im = (T)0;
+        bool any = false;
+        for (int t = arg; t < arg + nt; t++) {
+            const uint64_t out = terms[t].outside;
+            if ((base & out) != out) continue;
+            any = true;
+            const uint32_t lm = terms[t].lanemask;
+            cplx<T> v;
+            v.re = (T)terms[t].val[0];
+            v.im = (T)terms[t].val[1];
+            const cplx<T> fv = cmul(v, f);
+            if (((uint32_t)lane & lm) == lm) f = fv;
+        }
+        if (any) {
+#pragma unroll
+            for (int r = 0; r < NR; r++)
+                if ((rs >> r) & 1) a[r] = cmul(f, a[r]);
+        }
+    }
+}
+
 // One register tile of a sweep: tile index `tile` of the program at prog,
 // processed by the calling wavefront (lane = its lane id).
 template <typename T, int VB>
@@ -408,57 +457,38 @@ __device__ __forceinline__ void regtile_apply(cplx<T> *__restrict__ psi, const u
         for (int r = 0; r < NR; r++) a[r] = gload<T>(uniform_ptr(psi + (base + reg_offset<VB>(bq, r))) + loff);
     }
 
-    const cptr<RTOp> ops = (cptr<RTOp>)(prog + h->op_off);
     const cptr<DiagTerm> terms = (cptr<DiagTerm>)(prog + h->term_off);
     const int nops = h->nops;
-    for (int o = 0; o < nops; o++) {
-        const int kind = ops[o].kind;
-        const int arg = ops[o].a;
-        if (kind == RT_REG) {
-            reg_gate_dispatch<T, NR>(a, load_mat<T>(ops[o].u), arg, ops[o].form);
-        } else if (kind == RT_LANE) {
-            lane_gate_dispatch<T, NR>(a, load_mat<T>(ops[o].u), arg, lane, ops[o].form);
-        } else if (kind == RT_SIGNS) {
-            uint64_t par = 0;
-            const int nt = ops[o].nterms;
-            for (int t = arg; t < arg + nt; t++) {
-                const uint64_t out = terms[t].outside;
-                if ((base & out) != out) continue;
-                const uint32_t lm = terms[t].lanemask;
-                const uint64_t rs = terms[t].regset;
-                par ^= ((uint32_t)lane & lm) == lm ? rs : 0ull;
-            }
+    if constexpr (sizeof(T) == 4) {
+        // complex64: the 64-byte FP32 op records, the next one fetched while
+        // the current one runs (its scalar loads do not stall the wave)
+        const cptr<RTOpF> fops = (cptr<RTOpF>)(prog + h->fop_off);
+        int kind = 0, arg = 0, nt = 0, form = 0;
+        float uf[8];
+        if (nops > 0) {
+            kind = fops[0].kind; arg = fops[0].a; nt = fops[0].nterms; form = fops[0].form;
 #pragma unroll
-            for (int r = 0; r < NR; r++) {
-                if ((par >> r) & 1) { a[r].re = -a[r].re; a[r].im = -a[r].im; }
-            }
-        } else if (kind == RT_PHASE) {
-            // a group of phase terms sharing one register set: the product
-            // of the phases whose lane and outside bits match, per lane,
-            // then one multiplication of the group's registers
-            const int nt = ops[o].nterms;
-            const uint64_t rs = terms[arg].regset;
-            cplx<T> f;
-            f.re = (T)1;
-            f.im = (T)0;
-            bool any = false;
-            for (int t = arg; t < arg + nt; t++) {
-                const uint64_t out = terms[t].outside;
-                if ((base & out) != out) continue;
-                any = true;
-                const uint32_t lm = terms[t].lanemask;
-                cplx<T> v;
-                v.re = (T)terms[t].val[0];
-                v.im = (T)terms[t].val[1];
-                const cplx<T> fv = cmul(v, f);
-                if (((uint32_t)lane & lm) == lm) f = fv;
-            }
-            if (any) {
-#pragma unroll
-                for (int r = 0; r < NR; r++)
-                    if ((rs >> r) & 1) a[r] = cmul(f, a[r]);
-            }
+            for (int k = 0; k < 8; k++) uf[k] = fops[0].u[k];
         }
+        for (int o = 0; o < nops; o++) {
+            const int on = o + 1 < nops ? o + 1 : o;
+            const int kind_n = fops[on].kind, arg_n = fops[on].a, nt_n = fops[on].nterms, form_n = fops[on].form;
+            float un[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) un[k] = fops[on].u[k];
+            Mat2<T> u;
+#pragma unroll
+            for (int k = 0; k < 4; k++) { u.m[k].re = uf[2 * k]; u.m[k].im = uf[2 * k + 1]; }
+            regtile_op<T, NR>(a, kind, arg, nt, form, u, terms, base, lane);
+            kind = kind_n; arg = arg_n; nt = nt_n; form = form_n;
+#pragma unroll
+            for (int k = 0; k < 8; k++) uf[k] = un[k];
+        }
+    } else {
+        const cptr<RTOp> ops = (cptr<RTOp>)(prog + h->op_off);
+        for (int o = 0; o < nops; o++)
+            regtile_op<T, NR>(a, ops[o].kind, ops[o].a, ops[o].nterms, ops[o].form, load_mat<T>(ops[o].u), terms, base,
+                              lane);
     }
     // the Clifford forms leave a power of sqrt2: 2^sexp exactly, then 1/sqrt2
     const int sexp = h->sexp;

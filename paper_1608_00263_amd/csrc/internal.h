@@ -122,7 +122,18 @@ struct DiagTerm {           // 48 bytes
     uint64_t pad2;
 };
 
-struct RTHeader {           // 112 bytes
+// The same op in 64 bytes with an FP32 matrix: what a complex64 tile reads
+// per op (one scalar load, fetched while the previous op runs).
+struct RTOpF {              // 64 bytes
+    int32_t kind;
+    int32_t a;
+    int32_t nterms;
+    int32_t form;
+    float u[8];
+    int32_t pad[4];
+};
+
+struct RTHeader {           // 128 bytes
     int32_t nops;
     int32_t vbits;
     int32_t rq[8];          // register qubits, ascending
@@ -139,6 +150,8 @@ struct RTHeader {           // 112 bytes
                             // qubits 0..3); 4 and 5 give contiguous rows
     int32_t tq[8];          // the tile's qubits above 3 (lane qubits and
                             // register qubits), ascending: vbits + 2 entries
+    int32_t fop_off;        // byte offset of the RTOpF array from the header
+    int32_t pad2[3];
 };
 
 // LDS-tile ops

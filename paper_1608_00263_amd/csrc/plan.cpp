@@ -742,9 +742,21 @@ static void push_regtile(const RTProgram &P, int n, int dtype, OpType type, std:
     size_t hoff = push_struct(&plan->prog, h);
     size_t ooff = push_bytes(&plan->prog, P.ops.data(), P.ops.size() * sizeof(RTOp));
     size_t toff = push_bytes(&plan->prog, P.terms.data(), P.terms.size() * sizeof(DiagTerm));
+    std::vector<RTOpF> fops(P.ops.size());
+    for (size_t i = 0; i < P.ops.size(); i++) {
+        RTOpF &f = fops[i];
+        f = RTOpF{};
+        f.kind = P.ops[i].kind;
+        f.a = P.ops[i].a;
+        f.nterms = P.ops[i].nterms;
+        f.form = P.ops[i].form;
+        for (int j = 0; j < 8; j++) f.u[j] = (float)P.ops[i].u[j];
+    }
+    size_t foff = push_bytes(&plan->prog, fops.data(), fops.size() * sizeof(RTOpF));
     RTHeader *hp = reinterpret_cast<RTHeader *>(plan->prog.data() + hoff);
     hp->op_off = (int32_t)(ooff - hoff);
     hp->term_off = (int32_t)(toff - hoff);
+    hp->fop_off = (int32_t)(foff - hoff);
     Op op;
     op.type = type;
     op.vbits = P.h.vbits;
