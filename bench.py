@@ -8,8 +8,9 @@ their cross entropy.  Prints one JSON line.
 
 value      = algorithmic HBM bytes of the step / step time (GB/s); the
              bytes are the sweeps' reads + writes of the state, one state
-             read for the statistics, two for the sampler, and the sample
-             gathers;
+             read for the statistics, one for the sampler's bucket weights,
+             and a 16-amplitude run per sample (the cross entropy reuses the
+             norm of the statistics);
 roofline   = the dominant kernel (register-tile sweep), its algorithmic
              bytes per launch over its event-timed average duration;
 circuit_s  = seconds of the same circuit per planning mode (plain per-gate,
@@ -46,10 +47,10 @@ def kernel_sha1():
     return h.hexdigest()
 
 
-def measured_traffic(tile):
-    """HBM bytes per register-tile launch from the committed counter summary,
-    or None when the summary is missing, for another tile width, or older
-    than the kernel sources."""
+def profile_summary(tile):
+    """Key-value lines of the committed counter summary of the register-tile
+    sweep, or {} when it is missing, for another tile width, or older than
+    the kernel sources."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as fh:
@@ -58,10 +59,23 @@ def measured_traffic(tile):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
         if kv.get("source_sha1") != kernel_sha1() or int(kv.get("register_qubits", -1)) != tile:
-            return None
-        return float(kv["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
-        return None
+            return {}
+        return kv
+    except (OSError, ValueError):
+        return {}
+
+
+def measured_traffic(tile):
+    """HBM bytes per register-tile launch from the counter summary, or None."""
+    v = profile_summary(tile).get("traffic_bytes_per_launch")
+    return float(v) if v is not None else None
+
+
+def measured_valu_frac(tile):
+    """Vector-ALU issue share of the register-tile sweeps from the counter
+    summary (instructions over one per CU-cycle at 2.4 GHz), or None."""
+    v = profile_summary(tile).get("valu_frac")
+    return float(v) if v is not None else None
 
 
 def log(msg):
@@ -137,7 +151,7 @@ def main():
         ms, kinds, by = st.apply_timed(circ, a.mode, 0, a.tile, args=args, from_zero=True)
         mom = st.moments()
         xs = st.sample(m, 1002)
-        ce, dh, z = st.cross_entropy(xs)
+        ce, dh, z = st.cross_entropy(xs, norm=mom["norm"])
         return ms, kinds, by, mom, ce, dh
 
     log("device %s; circuit 5x6 d40: %d gates" % (dev_name, circ.ngates))
@@ -165,7 +179,7 @@ def main():
     t1 = time.perf_counter()
     step_s = (t1 - t0) / a.steps
     mom, ce, dh, nsweeps = last
-    step_bytes = sweep_bytes[-1] + S64 + 2 * S64 + m * 128.0
+    step_bytes = sweep_bytes[-1] + S64 + S64 + m * 128.0
     value = step_bytes / step_s / 1e9
     achieved = dom_bytes / (dom_ms / 1e3) / 1e9
     log("timed %d steps: %.2f ms/step, sweeps %.2f ms, %d sweeps" % (a.steps, step_s * 1e3,
@@ -193,6 +207,7 @@ def main():
                      "kernel": "k_regtile<float,%d>" % a.tile,
                      "launch_avg_ms": round(dom_ms / max(dom_launches, 1), 4),
                      "bytes_per_launch": round(dom_bytes / max(dom_launches, 1), 1),
+                     "valu_frac": measured_valu_frac(a.tile if a.mode == "regtile" else -1),
                      "kernel_sources_sha1": kernel_sha1()},
         "results": {"entropy": mom["entropy"], "unif_ce": mom["unif_ce"], "norm": mom["norm"],
                     "M2": mom["M2"], "M10": mom["M10"], "ce": ce, "delta_h": dh},
@@ -301,7 +316,7 @@ def c5_run(sv, C, torch):
     xs = st.sample(10 ** 6, 1005)
     t_sample = time.perf_counter() - t0
     t0 = time.perf_counter()
-    ce, dh, z = st.cross_entropy(xs)
+    ce, dh, z = st.cross_entropy(xs, norm=m["norm"])
     t_ce = time.perf_counter() - t0
     gbps = float(by.sum()) / (float(ms.sum()) / 1e3) / 1e9
     out.update({"circuit_s": round(dt, 4), "sweeps": len(ms), "sweep_ms_avg": round(float(ms.mean()), 3),

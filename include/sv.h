@@ -226,9 +226,11 @@ sv_status sv_sample_from(const double *probs, uint64_t N, const uint64_t *r64,
 
 /* Sample cross entropy of Eqs. (ae) and (5):
  *   ce = ln S - (1/k) sum_i ln p(x_i),  delta_h = ln 2^n + gamma - ce
- * over k samples (host array); S = sum_x p(x).  ce = +inf when some
- * p(x_i) = 0; *zero_samples (may be NULL) gets their number.  Synchronises. */
-sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k,
+ * over k samples (host array); S = sum_x p(x).  norm > 0 is taken as S (the
+ * norm sv_moments returned for the same state, which saves a pass over the
+ * state); norm <= 0 computes it.  ce = +inf when some p(x_i) = 0;
+ * *zero_samples (may be NULL) gets their number.  Synchronises. */
+sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k, double norm,
                            double *ce, double *delta_h, int64_t *zero_samples);
 
 /* Gradient of L(theta) = -(1/k) sum_i ln p_theta(x_i) with respect to

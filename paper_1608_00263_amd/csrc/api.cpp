@@ -457,12 +457,13 @@ sv_status sv_sample_from(const double *probs, uint64_t N, const uint64_t *r64, i
     return run_sample_from(probs, N, r64, k, out, (hipStream_t)hip_stream);
 }
 
-sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k, double *ce, double *delta_h,
-                           int64_t *zero_samples) {
+sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k, double norm, double *ce,
+                           double *delta_h, int64_t *zero_samples) {
     SV_TRY(check_state(st));
     if (k <= 0 || !samples || !ce) return fail(SV_EINVAL, "need k > 0 samples and an output");
-    double S = 0;
-    SV_TRY(run_norm(st, st->data, &S));
+    if (!(norm <= 0.0 || std::isfinite(norm))) return fail(SV_EINVAL, "norm must be finite");
+    double S = norm;
+    if (!(norm > 0.0)) SV_TRY(run_norm(st, st->data, &S));
     SV_TRY(st->ws2.reserve((size_t)k * 8));
     uint64_t *dx = (uint64_t *)st->ws2.ptr;
     SV_HIP(hipMemcpyAsync(dx, samples, (size_t)k * 8, hipMemcpyHostToDevice, st->stream));

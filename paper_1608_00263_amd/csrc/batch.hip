@@ -94,7 +94,7 @@ __device__ __forceinline__ void run_item(const BRound &R, const BInst &I, uint64
     double acc[NSTAT];
 #pragma unroll
     for (int q = 0; q < NSTAT; q++) acc[q] = 0.0;
-    unsigned long long zeros = 0;
+    unsigned zeros = 0;
     const double Nd = ldexp(1.0, I.n);
     const gptr<cpx<float>> src =
         (gptr<cpx<float>>)(reinterpret_cast<cpx<float> *>(I.psi) + (chunk << STAT_BITS));
@@ -107,24 +107,7 @@ __device__ __forceinline__ void run_item(const BRound &R, const BInst &I, uint64
             buf[v].im = src[j0 + v * BLOCK].im;
         }
 #pragma unroll
-        for (int v = 0; v < UNR; v++) {
-            const double p = prob_of(buf[v]);
-            acc[0] += p;
-            if (p > 0.0) {
-                const double l = log(p);
-                acc[1] = fma(p, l, acc[1]);
-                acc[2] += l;
-            } else {
-                zeros++;
-            }
-            const double u = Nd * p;
-            double uk = u;
-#pragma unroll
-            for (int k = 0; k < 10; k++) {
-                acc[3 + k] += uk;
-                uk *= u;
-            }
-        }
+        for (int v = 0; v < UNR; v++) stat_add(acc, zeros, prob_of(buf[v]), Nd);
     }
     block_sum<double, NSTAT>(acc, red);
     zeros = wave_sum(zeros);

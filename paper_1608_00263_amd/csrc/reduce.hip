@@ -36,44 +36,32 @@ template <typename T, bool FULL>
 __global__ __launch_bounds__(RB) void k_stats(const cpx<T> *__restrict__ psi, uint64_t chunk,
                                               double Nd, double *__restrict__ part) {
     __shared__ double red[4 * NSTAT];
-    __shared__ unsigned long long zred[4];
+    __shared__ unsigned zred[4];
     double acc[NSTAT];
 #pragma unroll
     for (int i = 0; i < NSTAT; i++) acc[i] = 0.0;
-    unsigned long long zeros = 0;
+    unsigned zeros = 0;
     const uint64_t start = (uint64_t)blockIdx.x * chunk;
-    // UNR loads in flight per thread before any use (chunk is a multiple of
-    // RB * UNR whenever the state has at least 2^12 amplitudes)
+    // UNR loads in flight per thread before any use over the whole multiple
+    // of RB * UNR (all of the chunk once the state has 2^12 amplitudes),
+    // then one amplitude per thread and step over the rest
     constexpr int UNR = 8;
-    const uint64_t step = (chunk % (RB * UNR) == 0) ? RB * UNR : RB;
-    const int unr = (step == RB * UNR) ? UNR : 1;
-    for (uint64_t j0 = start + threadIdx.x; j0 < start + chunk; j0 += step) {
-      cpx<T> buf[UNR];
+    const uint64_t end = start + chunk, main_end = end - chunk % (RB * UNR);
+    for (uint64_t j0 = start + threadIdx.x; j0 < main_end; j0 += RB * UNR) {
+        cpx<T> buf[UNR];
 #pragma unroll
-      for (int u = 0; u < UNR; u++)
-          if (u < unr) buf[u] = psi[j0 + (uint64_t)u * RB];
+        for (int u = 0; u < UNR; u++) buf[u] = psi[j0 + (uint64_t)u * RB];
 #pragma unroll
-      for (int u = 0; u < UNR; u++) {
-        if (u >= unr) break;
-        const double p = prob_of(buf[u]);
-        acc[0] += p;
-        if (FULL) {
-            if (p > 0.0) {
-                const double l = log(p);
-                acc[1] = fma(p, l, acc[1]);
-                acc[2] += l;
-            } else {
-                zeros++;
-            }
-            const double u = Nd * p;
-            double uk = u;
-#pragma unroll
-            for (int k = 0; k < 10; k++) {
-                acc[3 + k] += uk;
-                uk *= u;
-            }
+        for (int u = 0; u < UNR; u++) {
+            const double p = prob_of(buf[u]);
+            if (FULL) stat_add(acc, zeros, p, Nd);
+            else acc[0] += p;
         }
-      }
+    }
+    for (uint64_t j = main_end + threadIdx.x; j < end; j += RB) {
+        const double p = prob_of(psi[j]);
+        if (FULL) stat_add(acc, zeros, p, Nd);
+        else acc[0] += p;
     }
     block_sum<double, NSTAT>(acc, red);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -82,7 +70,7 @@ __global__ __launch_bounds__(RB) void k_stats(const cpx<T> *__restrict__ psi, ui
     __syncthreads();
     if (threadIdx.x < NSTAT) part[(uint64_t)blockIdx.x * 16 + threadIdx.x] = red[threadIdx.x];
     if (threadIdx.x == NSTAT) {
-        unsigned long long z = zred[0] + zred[1] + zred[2] + zred[3];
+        const unsigned long long z = (unsigned long long)zred[0] + zred[1] + zred[2] + zred[3];
         part[(uint64_t)blockIdx.x * 16 + NSTAT] = (double)z;
     }
 }

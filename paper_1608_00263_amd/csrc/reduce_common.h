@@ -50,4 +50,60 @@ __device__ __forceinline__ void block_sum(V (&v)[NV], V *red /* LDS, 4*NV */) {
 
 constexpr int NSTAT = 13;   // S, sum p ln p, sum ln p, sum u^k (k = 1..10)
 
+// Natural logarithm of a positive finite double, to a few units in the last
+// place (about 30 FP64 operations, no table, no branch).  With
+// x = 2^e m, m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s) for
+// s = (m - 1) / (m + 1), |s| <= 0.1716, summed as the odd series
+// 2 (s + s^3/3 + ... + s^19/19); the first omitted term is below 3e-17 of
+// ln m.  ln 2 is split into a 32-bit head, so e * LN2_HI is exact, and the
+// remainder.  ln 1 = 0 exactly.
+__device__ __forceinline__ double ln_pos(double x) {
+    constexpr double LN2_HI = 6.93147180369123816490e-01;   // 0x3fe62e42fee00000
+    constexpr double LN2_LO = 1.90821492927058770002e-10;   // ln 2 - LN2_HI
+    int e;
+    double m = frexp(x, &e);                                 // m in [1/2, 1)
+    const bool lo = m < 0.70710678118654752440;
+    m = lo ? m + m : m;
+    e = lo ? e - 1 : e;
+    const double f = m - 1.0;                                // exact
+    const double d = m + 1.0;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    double s = f * r;
+    s = fma(fma(-s, d, f), r, s);                           // s = f / d, corrected
+    const double z = s * s;
+    double q = 2.0 / 19.0;
+    q = fma(q, z, 2.0 / 17.0);
+    q = fma(q, z, 2.0 / 15.0);
+    q = fma(q, z, 2.0 / 13.0);
+    q = fma(q, z, 2.0 / 11.0);
+    q = fma(q, z, 2.0 / 9.0);
+    q = fma(q, z, 2.0 / 7.0);
+    q = fma(q, z, 2.0 / 5.0);
+    q = fma(q, z, 2.0 / 3.0);
+    const double lnm = fma(s * z, q, s + s);
+    const double de = (double)e;
+    return fma(de, LN2_HI, fma(de, LN2_LO, lnm));
+}
+
+// Adds one probability p to the one-pass statistics: acc = {S, sum p ln p,
+// sum ln p, sum u^k for k = 1..10} with u = N p, and counts p = 0 (those
+// contribute 0 to both log sums).
+__device__ __forceinline__ void stat_add(double (&acc)[NSTAT], unsigned &zeros, double p, double Nd) {
+    acc[0] += p;
+    const bool pos = p > 0.0;
+    const double l = pos ? ln_pos(pos ? p : 1.0) : 0.0;
+    acc[1] = fma(p, l, acc[1]);
+    acc[2] += l;
+    zeros += pos ? 0u : 1u;
+    const double u = Nd * p;
+    double uk = u;
+#pragma unroll
+    for (int k = 0; k < 10; k++) {
+        acc[3 + k] += uk;
+        uk *= u;
+    }
+}
+
 }  // namespace svi

@@ -80,7 +80,7 @@ EXPORTS = {
                                  ctypes.c_int]),
     "sv_sample_from": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                       ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
-    "sv_cross_entropy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+    "sv_cross_entropy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sv_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
@@ -257,13 +257,16 @@ class State:
         check(lib().sv_sample(self.h, k, ctypes.c_uint64(seed), _ptr(out), 0))
         return out[:k]
 
-    def cross_entropy(self, samples: np.ndarray):
+    def cross_entropy(self, samples: np.ndarray, norm=None):
+        """(ce, delta_h, zero_samples) of the samples; norm, when given, is
+        the state's sum of probabilities (moments()["norm"] of the same
+        state), which saves the pass that computes it."""
         x = np.ascontiguousarray(samples, dtype=np.uint64)
         ce = ctypes.c_double()
         dh = ctypes.c_double()
         z = ctypes.c_int64()
-        check(lib().sv_cross_entropy(self.h, _ptr(x), x.size, ctypes.byref(ce), ctypes.byref(dh),
-                                     ctypes.byref(z)))
+        check(lib().sv_cross_entropy(self.h, _ptr(x), x.size, 0.0 if norm is None else float(norm),
+                                     ctypes.byref(ce), ctypes.byref(dh), ctypes.byref(z)))
         return ce.value, dh.value, z.value
 
     def backward(self, circ, samples: np.ndarray, checkpoint_c: int = 0, mode="auto", k_max=0,

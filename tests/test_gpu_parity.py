@@ -126,6 +126,23 @@ def test_moments_identical_input(dtype):
     st.close()
 
 
+def test_moments_wide_range_c128():
+    # probabilities from 1 down to the FP64 subnormal range exercise every
+    # binary exponent of the logarithm's argument reduction
+    n = 12
+    rng = np.random.default_rng(5)
+    mag = 10.0 ** rng.uniform(-161.0, 0.0, size=1 << n)
+    psi = mag * np.exp(1j * rng.uniform(0.0, 2.0 * np.pi, size=1 << n))
+    psi[7] = 1.0
+    st = sv.State(n, "c128", tensor=torch.from_numpy(psi).to("cuda"))
+    got = st.moments()
+    want = oracle.stats(oracle.probs(psi))
+    for key in ("norm", "entropy", "unif_ce"):
+        assert abs(got[key] - want[key]) <= 1e-12 * max(1, abs(want[key])), key
+    np.testing.assert_allclose(got["moments"], want["moments"], rtol=1e-11)
+    st.close()
+
+
 def test_moments_edge_cases():
     n = 12
     st = sv.State(n, "c64")
@@ -151,6 +168,13 @@ def test_c1_statistics_and_ce(c1):
     ce, dh, z = st.cross_entropy(xs)
     ce0, dh0, z0 = oracle.cross_entropy(oracle.probs(ref), xs)
     assert abs(ce - ce0) <= 1e-4 and abs(dh - dh0) <= 1e-4 and z == z0 == 0
+    # a norm passed in replaces the pass that computes it: ce = ln S - mean ln p
+    ce1, dh1, _ = st.cross_entropy(xs, norm=got["norm"])
+    assert abs(ce1 - ce) <= 1e-12
+    ce2, dh2, _ = st.cross_entropy(xs, norm=2.0 * got["norm"])
+    assert abs(ce2 - ce - math.log(2.0)) <= 1e-12 and abs(dh2 - dh + math.log(2.0)) <= 1e-12
+    with pytest.raises(sv.SVError):
+        st.cross_entropy(xs, norm=float("inf"))
     st.close()
 
 
