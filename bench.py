@@ -272,7 +272,7 @@ def mode_timings(sv, C, circ, torch):
             st.apply(circ, mode, k, t, args=args, from_zero=True, no_mfma=nomf)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            sw, by = st.plan_info(circ, mode, k, t, no_mfma=nomf)
+            sw, by = st.plan_info(circ, mode, k, t, no_mfma=nomf, from_zero=True)
             key = "%s_%s%s%s" % (dtype, mode, ("_k%d" % k if k else "") + ("_t%d" % t if t else ""),
                                  "_valu" if nomf else "")
             res[key] = {"s": round(dt, 4), "sweeps": sw, "GBps": round(by / dt / 1e9, 1)}

@@ -286,24 +286,26 @@ extern "C" sv_status sv_host_plan_describe(const sv_circuit *c, sv_dtype dt, con
     Plan plan;
     SV_TRY(host_plan(c, dt, opts, from_zero, &plan));
     std::string out;
-    char line[256];
+    char line[512];
     for (size_t i = 0; i < plan.ops.size(); i++) {
         const Op &op = plan.ops[i];
         if (op.type == OP_REGTILE) {
             const RTHeader *h = (const RTHeader *)(plan.prog.data() + op.prog_off);
             const RTOp *ops = (const RTOp *)((const uint8_t *)h + h->op_off);
             int nreg = 0, nlane = 0, nsign = 0, nterm = 0, nphase = 0;
-            int nform[12] = {0};
+            int nform[12] = {0}, nbit[6] = {0};
             for (int o = 0; o < h->nops; o++) {
                 if (ops[o].kind == RT_REG || ops[o].kind == RT_LANE) nform[std::min(11, std::max(0, (int)ops[o].form))]++;
                 if (ops[o].kind == RT_REG) nreg++;
-                else if (ops[o].kind == RT_LANE) nlane++;
+                else if (ops[o].kind == RT_LANE) { nlane++; nbit[std::min(5, std::max(0, (int)ops[o].a))]++; }
                 else if (ops[o].kind == RT_SIGNS) { nsign++; nterm += ops[o].nterms; }
                 else nphase++;
             }
             std::string rq;
             for (int j = 0; j < h->vbits; j++) rq += (j ? "," : "") + std::to_string(h->rq[j]);
             rq += "] lanes=[" + std::to_string(h->lq[0]) + "," + std::to_string(h->lq[1]);
+            rq += "] lanebits=[";
+            for (int b = 0; b < 6; b++) rq += (b ? "," : "") + std::to_string(nbit[b]);
             std::string fs;
             static const char *fname[12] = {"gen", "h", "sx", "sy", "sxdg", "sydg", "phase", "rx", "ry", "real",
                                             "trx", "try"};

@@ -227,9 +227,11 @@ class State:
         name = {v: k for k, v in MODES.items()}[o.mode]
         return name, o.k_max, o.tile_qubits, bool(done.value), o.sweep_budget
 
-    def plan_info(self, circ, mode="auto", k_max=0, tile=0, no_mfma=False, budget=0):
+    def plan_info(self, circ, mode="auto", k_max=0, tile=0, no_mfma=False, budget=0, from_zero=False):
+        """(sweeps, algorithmic bytes) of the plan apply() runs with the same
+        arguments."""
         a = CircuitArgs(circ)
-        o = make_opts(mode, k_max, tile, no_mfma=no_mfma, budget=budget)
+        o = make_opts(mode, k_max, tile, from_zero=from_zero, no_mfma=no_mfma, budget=budget)
         sw = ctypes.c_int64()
         by = ctypes.c_double()
         check(lib().sv_plan_info(self.h, a.ref, ctypes.byref(o), ctypes.byref(sw), ctypes.byref(by)))
