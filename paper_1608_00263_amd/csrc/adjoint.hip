@@ -57,6 +57,19 @@ __device__ __forceinline__ T im_cm(cplx<T> a, cplx<T> b) { return fma(a.re, b.im
 template <typename T>
 __device__ __forceinline__ T re_cm(cplx<T> a, cplx<T> b) { return fma(a.re, b.re, a.im * b.im); }
 
+// acc += s Im conj(a) b and acc += s Re conj(a) b as two fused multiply-adds
+// (s = +1 or -1 at compile time)
+template <int SG, typename T>
+__device__ __forceinline__ void acc_im_cm(T &acc, cplx<T> a, cplx<T> b) {
+    acc = fma((T)SG * a.re, b.im, acc);
+    acc = fma((T)(-SG) * a.im, b.re, acc);
+}
+template <int SG, typename T>
+__device__ __forceinline__ void acc_re_cm(T &acc, cplx<T> a, cplx<T> b) {
+    acc = fma((T)SG * a.re, b.re, acc);
+    acc = fma((T)SG * a.im, b.im, acc);
+}
+
 // This lane's share of Re <mu| D |phi> for D on register slot S.  Closed
 // forms for the generators of the parametrised gates (pairs (0, 1) of the
 // slot): RX: D = -(i/2) X gives (1/2) [Im conj(mu0) phi1 + Im conj(mu1) phi0];
@@ -77,16 +90,25 @@ __device__ __forceinline__ double grad_reg_g(const cplx<T> (&phi)[NR], const cpl
         }
         return acc;
     } else {
-        T acc = 0;
+        // two accumulators, so that the multiply-add chains are half as long
+        T acc[2] = {0, 0};
+        int k = 0;
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             if (r & (1 << S)) continue;
             const int r1 = r | (1 << S);
-            if constexpr (G == G_RX) acc += im_cm(mu[r], phi[r1]) + im_cm(mu[r1], phi[r]);
-            else if constexpr (G == G_RY) acc += re_cm(mu[r1], phi[r]) - re_cm(mu[r], phi[r1]);
-            else acc -= im_cm(mu[r1], phi[r1]);
+            if constexpr (G == G_RX) {
+                acc_im_cm<1>(acc[0], mu[r], phi[r1]);
+                acc_im_cm<1>(acc[1], mu[r1], phi[r]);
+            } else if constexpr (G == G_RY) {
+                acc_re_cm<1>(acc[0], mu[r1], phi[r]);
+                acc_re_cm<-1>(acc[1], mu[r], phi[r1]);
+            } else {
+                acc_im_cm<-1>(acc[k & 1], mu[r1], phi[r1]);
+                k++;
+            }
         }
-        return (G == G_P ? 1.0 : 0.5) * (double)acc;
+        return (G == G_P ? 1.0 : 0.5) * (double)(acc[0] + acc[1]);
     }
 }
 
@@ -122,10 +144,10 @@ __device__ __forceinline__ double grad_lane_g(const cplx<T> (&phi)[NR], const cp
                                               const Mat2<T> &d, int lane) {
     const bool hi = (lane >> B) & 1;
     if constexpr (G == G_P) {
-        T acc = 0;
+        T acc[2] = {0, 0};
 #pragma unroll
-        for (int r = 0; r < NR; r++) acc -= im_cm(mu[r], phi[r]);
-        return hi ? (double)acc : 0.0;
+        for (int r = 0; r < NR; r++) acc_im_cm<-1>(acc[r & 1], mu[r], phi[r]);
+        return hi ? (double)(acc[0] + acc[1]) : 0.0;
     } else if constexpr (G == G_GEN) {
         cplx<T> cs = hi ? d.m[3] : d.m[0];
         cplx<T> cp = hi ? d.m[2] : d.m[1];
@@ -139,17 +161,18 @@ __device__ __forceinline__ double grad_lane_g(const cplx<T> (&phi)[NR], const cp
         }
         return acc;
     } else {
-        T acc = 0;
+        T acc[2] = {0, 0};
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             cplx<T> p;
             p.re = lane_xor<B>(phi[r].re);
             p.im = lane_xor<B>(phi[r].im);
-            if constexpr (G == G_RX) acc += im_cm(mu[r], p);
-            else acc += re_cm(mu[r], p);
+            if constexpr (G == G_RX) acc_im_cm<1>(acc[r & 1], mu[r], p);
+            else acc_re_cm<1>(acc[r & 1], mu[r], p);
         }
-        if constexpr (G == G_RY) acc = hi ? acc : -acc;
-        return 0.5 * (double)acc;
+        T a = acc[0] + acc[1];
+        if constexpr (G == G_RY) a = hi ? a : -a;
+        return 0.5 * (double)a;
     }
 }
 
@@ -186,7 +209,7 @@ __device__ __forceinline__ double grad_lane_dispatch(const cplx<T> (&phi)[NR], c
 template <typename T, int NR, int B, int FORM>
 __device__ __forceinline__ double lane_rot_grad_gate(cplx<T> (&phi)[NR], cplx<T> (&mu)[NR], const Mat2<T> &u) {
     static_assert(B == 4 || B == 5, "half swaps exist for lane bits 4 and 5");
-    T acc = 0;
+    T acc[2] = {0, 0};
 #pragma unroll
     for (int r = 0; r < NR; r += 2) {
         cplx<T> x = phi[r], y = phi[r + 1], mx = mu[r], my = mu[r + 1];
@@ -194,8 +217,13 @@ __device__ __forceinline__ double lane_rot_grad_gate(cplx<T> (&phi)[NR], cplx<T>
         half_swap<B>(x.im, y.im);
         half_swap<B>(mx.re, my.re);
         half_swap<B>(mx.im, my.im);
-        if constexpr (FORM == F_TRX) acc += im_cm(mx, y) + im_cm(my, x);
-        else acc += re_cm(my, x) - re_cm(mx, y);
+        if constexpr (FORM == F_TRX) {
+            acc_im_cm<1>(acc[0], mx, y);
+            acc_im_cm<1>(acc[1], my, x);
+        } else {
+            acc_re_cm<1>(acc[0], my, x);
+            acc_re_cm<-1>(acc[1], mx, y);
+        }
         pair_form<T, FORM>(x, y, u);
         pair_form<T, FORM>(mx, my, u);
         half_swap<B>(x.re, y.re);
@@ -207,7 +235,7 @@ __device__ __forceinline__ double lane_rot_grad_gate(cplx<T> (&phi)[NR], cplx<T>
         mu[r] = mx;
         mu[r + 1] = my;
     }
-    return 0.5 * (double)acc;
+    return 0.5 * (double)(acc[0] + acc[1]);
 }
 
 template <typename T, int NR>
@@ -350,10 +378,19 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
                 cplx<T> dv;
                 dv.re = (T)ops[o].d[6];
                 dv.im = (T)ops[o].d[7];
-                double g = 0;
+                // Re <mu| dv |phi> over the set's registers = Re dv W with
+                // W = sum conj(mu) phi, accumulated in two halves
+                T wr[2] = {0, 0}, wi[2] = {0, 0};
 #pragma unroll
-                for (int r = 0; r < NR; r++)
-                    if ((rs >> r) & 1) g += (double)re_cm(mu[r], cmul(dv, phi[r]));
+                for (int r = 0; r < NR; r++) {
+                    const bool on = (rs >> r) & 1;
+                    cplx<T> pz;
+                    pz.re = on ? phi[r].re : (T)0;
+                    pz.im = on ? phi[r].im : (T)0;
+                    acc_re_cm<1>(wr[r & 1], mu[r], pz);
+                    acc_im_cm<1>(wi[r & 1], mu[r], pz);
+                }
+                double g = (double)dv.re * (double)(wr[0] + wr[1]) - (double)dv.im * (double)(wi[0] + wi[1]);
                 g = wave_sum_d<T>(g) * ops[o].gscale;
                 if (lane == 0) gpart[tile * (uint64_t)nslots + slot] = g;
             }
