@@ -1,6 +1,15 @@
-"""Full-size GPU checks: the 35-qubit, depth-40 circuit of the 5x7 grid in
-complex64 (a 256 GiB state), checked through properties that hold at any
-size, since no reference can hold the state:
+"""Full-size GPU checks.
+
+The benchmark's own workload, the 30-qubit depth-40 circuit of the 5x6 grid
+in complex64 with register tiles of 6 qubits (the launch configuration the
+benchmark times), is checked against two other computations of the same
+state on the GPU: complex128 per-gate sweeps (a different kernel family and
+precision) and complex128 register tiles; and its Clifford variant against a
+stabilizer tableau.
+
+The 35-qubit, depth-40 circuit of the 5x7 grid in complex64 (a 256 GiB
+state) is checked through properties that hold at any size, since no
+reference can hold the state:
 
 * the Clifford variant (T replaced by S) against a stabilizer tableau: the
   probability of every sampled bit string is exactly 2^-r, the entropy is
@@ -52,24 +61,75 @@ def st35():
     torch.cuda.empty_cache()
 
 
-def test_c5_clifford_variant_vs_tableau(st35):
+@pytest.fixture
+def st30():
+    # per test, so that nothing of it is held when the 35-qubit state needs
+    # all but a few GiB of the device
+    print("allocating the 30-qubit state", flush=True)
+    st = sv.State(30, "c64")
+    yield st
+    st.close()
+    del st
+    torch.cuda.empty_cache()
+
+
+def _check_clifford(st, circ, n, nsamp, seed):
     from tests.stabilizer import run_clifford
-    circ = C.make_circuit(5, 7, 40, seed=5, clifford=True)
-    print("clifford variant: %d gates" % circ.ngates, flush=True)
-    st35.apply(circ, "regtile", 0, 6, from_zero=True)
-    m = st35.moments()
+    m = st.moments()
     tab = run_clifford(circ)
     r = tab.num_random()
     assert abs(m["norm"] - 1.0) < 1e-5
     assert abs(m["entropy"] - r * math.log(2.0)) < 1e-4
-    assert m["zero_count"] == 2 ** 35 - 2 ** r
-    xs = st35.sample(64, 77)
+    assert m["zero_count"] == 2 ** n - 2 ** r
+    xs = st.sample(nsamp, seed)
     for x in xs:
-        bits = [(int(x) >> q) & 1 for q in range(35)]
+        bits = [(int(x) >> q) & 1 for q in range(n)]
         want = tab.probability(bits)
-        got = float(st35.probs(int(x), 1).cpu()[0])
+        got = float(st.probs(int(x), 1).cpu()[0])
         assert want == 2.0 ** -r
         assert abs(got / want - 1.0) < 1e-4, (int(x), got, want)
+
+
+def test_c2_clifford_variant_vs_tableau(st30):
+    circ = C.make_circuit(5, 6, 40, seed=2, clifford=True)
+    st30.apply(circ, "regtile", 0, 6, from_zero=True)
+    _check_clifford(st30, circ, 30, 64, 78)
+
+
+def test_c2_register_tiles_vs_per_gate_c128(st30):
+    circ = C.make_circuit(5, 6, 40, seed=2)
+    print("30 qubits: complex64 register tiles", flush=True)
+    st30.apply(circ, "regtile", 0, 6, from_zero=True)
+    m64 = st30.moments()
+    xs = st30.sample(10 ** 5, 1002)
+    ce64, dh64, _ = st30.cross_entropy(xs, norm=m64["norm"])
+    print("30 qubits: complex128 per-gate sweeps", flush=True)
+    ref = sv.State(30, "c128")
+    ref.apply(circ, "plain", from_zero=True)
+    d = float(torch.linalg.vector_norm(st30.tensor.to(torch.complex128) - ref.tensor))
+    assert d <= 1e-4, d
+    m128 = ref.moments()
+    assert abs(m64["entropy"] - m128["entropy"]) <= 1e-4
+    assert abs(m64["unif_ce"] - m128["unif_ce"]) <= 1e-4
+    np.testing.assert_allclose(m64["moments"], m128["moments"], rtol=1e-3)
+    ce128, dh128, _ = ref.cross_entropy(xs)
+    assert abs(ce64 - ce128) <= 1e-4 and abs(dh64 - dh128) <= 1e-4
+    print("30 qubits: complex128 register tiles", flush=True)
+    rt = sv.State(30, "c128")
+    rt.apply(circ, "regtile", 0, 5, from_zero=True)
+    d128 = float(torch.linalg.vector_norm(rt.tensor - ref.tensor))
+    assert d128 <= 1e-11, d128
+    rt.close()
+    ref.close()
+    del rt, ref
+    torch.cuda.empty_cache()
+
+
+def test_c5_clifford_variant_vs_tableau(st35):
+    circ = C.make_circuit(5, 7, 40, seed=5, clifford=True)
+    print("clifford variant: %d gates" % circ.ngates, flush=True)
+    st35.apply(circ, "regtile", 0, 6, from_zero=True)
+    _check_clifford(st35, circ, 35, 64, 77)
 
 
 def test_c5_circuit_then_inverse_is_identity(st35):
