@@ -182,6 +182,7 @@ def main():
     step_bytes = sweep_bytes[-1] + S64 + S64 + m * 128.0
     value = step_bytes / step_s / 1e9
     achieved = dom_bytes / (dom_ms / 1e3) / 1e9
+    floor = sweep_floor(sv, C, st, a.tile if a.mode == "regtile" else 6)
     log("timed %d steps: %.2f ms/step, sweeps %.2f ms, %d sweeps" % (a.steps, step_s * 1e3,
                                                                         np.mean(sweep_ms), nsweeps))
     out = {
@@ -208,6 +209,8 @@ def main():
                      "launch_avg_ms": round(dom_ms / max(dom_launches, 1), 4),
                      "bytes_per_launch": round(dom_bytes / max(dom_launches, 1), 1),
                      "valu_frac": measured_valu_frac(a.tile if a.mode == "regtile" else -1),
+                     "achievable": floor["GBps"], "frac_of_achievable": round(achieved / floor["GBps"], 4),
+                     "achievable_how": floor["how"],
                      "kernel_sources_sha1": kernel_sha1()},
         "results": {"entropy": mom["entropy"], "unif_ce": mom["unif_ce"], "norm": mom["norm"],
                     "M2": mom["M2"], "M10": mom["M10"], "ce": ce, "delta_h": dh},
@@ -229,6 +232,24 @@ def main():
         log("cpu baseline (%.0f s budget)" % a.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(circ, a.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def sweep_floor(sv, C, st, tile):
+    """The second denominator of the roofline: the same register-tile sweep
+    kernel with a one-gate program (one X^1/2 on the top qubit, register
+    tile rows of 64 contiguous amplitudes), reading and writing the whole
+    state; best of five launches."""
+    import numpy as np
+    one = C.Circuit(n=st.n, gates=C.make_gates([(C.SX, st.n - 1, -1, 1, -1, -1)]))
+    best = None
+    for _ in range(6):
+        ms, kinds, by = st.apply_timed(one, "regtile", 0, tile)
+        t = float(ms.sum())
+        best = t if best is None else min(best, t)
+    gbps = 2.0 * 8.0 * 2 ** st.n / (best / 1e3) / 1e9
+    log("one-gate sweep: %.3f ms = %.0f GB/s" % (best, gbps))
+    return {"GBps": round(gbps, 1), "how": "k_regtile<float,%d> with a one-gate program, best of 6 launches "
+                                           "(%.3f ms for 2 x 8 GiB)" % (tile, best)}
 
 
 def copy_probe(torch):
