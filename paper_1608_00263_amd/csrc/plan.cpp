@@ -1210,9 +1210,9 @@ sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int che
         return fail(SV_EINVAL, "sv_backward: the circuit must open with a Hadamard on every qubit");
     }
     fold_diagonals(&g, rq.n, true);
-    int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 4 : 3);
+    int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 5 : 3);
     vb = std::max(1, std::min(vb, rq.dtype == SV_C64 ? 5 : 4));
-    vb = std::min(vb, rq.n - LANE_BITS - 2);
+    vb = std::max(1, std::min(vb, rq.n - LANE_BITS - 2));
     // segments of consecutive gates between checkpoints
     std::vector<std::vector<SGate>> segs(1);
     int cur = 0;

@@ -232,6 +232,25 @@ def test_adjoint_vs_oracle(dtype, ck):
         assert np.linalg.norm(g - g0) <= 1e-3 * np.linalg.norm(g0)
 
 
+@pytest.mark.parametrize("dtype,rows,cols,tiles", [("c64", 2, 4, (0,)), ("c64", 3, 3, (0,)),
+                                                    ("c64", 3, 4, (1, 2, 3, 4, 5)),
+                                                    ("c128", 2, 4, (0,)), ("c128", 3, 4, (1, 2, 3, 4))])
+def test_adjoint_small_sizes_and_tile_widths(dtype, rows, cols, tiles):
+    # the smallest sizes (a tile of 7 qubits at n = 8) and every reverse-sweep
+    # tile width, against the FP64 adjoint
+    circ = C.make_circuit(rows, cols, 12, seed=63, parametrise=True, theta_seed=64, theta_std=0.05)
+    p0 = oracle.probs(oracle.apply_circuit(circ.with_theta(np.zeros(circ.nparams))))
+    xs = oracle.sample(p0, 1000, 1007)
+    loss0, g0 = oracle.adjoint(circ, xs)
+    st = sv.State(circ.n, dtype)
+    for t in tiles:
+        loss, g = st.backward(circ, xs, tile=t)
+        tol = 1e-9 if dtype == "c128" else 1e-4
+        assert abs(loss - loss0) < tol, t
+        assert np.abs(g - g0).max() < tol, t
+    st.close()
+
+
 # ---------------------------------------------------------------------------
 # ensemble
 # ---------------------------------------------------------------------------
