@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3   # dense FP32 matrix peak of the MI355X
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_regtile_c2_traffic.txt")
 # sources of the register-tile sweep and its programs: the counter-based
 # traffic of the profile summary is reported only while these are unchanged
@@ -297,6 +298,14 @@ def mode_timings(sv, C, circ, torch):
             key = "%s_%s%s%s" % (dtype, mode, ("_k%d" % k if k else "") + ("_t%d" % t if t else ""),
                                  "_valu" if nomf else "")
             res[key] = {"s": round(dt, 4), "sweeps": sw, "GBps": round(by / dt / 1e9, 1)}
+            if mode in ("fused", "tiled"):
+                tot, mf = dense_block_flops(sv, circ, dtype, mode, k, t, nomf)
+                res[key]["dense_TFLOPs"] = round(tot / dt / 1e12, 2)
+                if mf:
+                    # MFMA block flops over the whole circuit time: a lower
+                    # bound on the rate of the matrix cores while they run
+                    res[key]["mfma_TFLOPs"] = round(mf / dt / 1e12, 2)
+                    res[key]["mfma_frac_of_peak"] = round(mf / dt / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4)
             if mode == "auto":
                 res[key]["choice"] = st.autotune(circ, from_zero=True)[:3]
             log("%s: %.3f s, %d sweeps" % (key, dt, sw))
@@ -304,6 +313,24 @@ def mode_timings(sv, C, circ, torch):
         del st
         torch.cuda.empty_cache()
     return res
+
+
+def dense_block_flops(sv, circ, dtype, mode, k, t, nomf):
+    """Algorithmic flops of the plan's dense 2^k blocks (8 * 2^k per
+    amplitude each: a complex 2^k x 2^k matrix on every 2^k-vector), and of
+    those that run on MFMA, read from the host description of the plan."""
+    import re
+    d = sv.host_plan_describe(circ, dtype, mode, k, t, from_zero=True, no_mfma=nomf)
+    N = float(2 ** circ.n)
+    tot = mf = 0.0
+    for blocks, m in re.findall(r"blocks=\[([0-9]*)\][^\n]*mfma=(\d)", d):
+        for ch in blocks:
+            kk = int(ch)
+            f = 8.0 * 2 ** kk * N
+            tot += f
+            if m == "1" and kk >= 4:
+                mf += f
+    return tot, mf
 
 
 def c5_run(sv, C, torch):

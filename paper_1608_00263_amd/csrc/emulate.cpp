@@ -250,6 +250,7 @@ static sv_status host_plan(const sv_circuit *c, sv_dtype dt, const sv_opts *o, i
     if (rq.budget != 0 && (rq.budget < 20 || rq.budget > 2000)) return fail(SV_EINVAL, "sweep_budget must be 0 or 20..2000");
     rq.from_zero = from_zero != 0;
     rq.force_zero = o && (o->flags & SV_FLAG_FROM_ZERO);
+    rq.no_mfma = o && (o->flags & SV_FLAG_NO_MFMA);
     return build_plan(c, rq, plan);
 }
 

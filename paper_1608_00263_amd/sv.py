@@ -321,9 +321,9 @@ def apply_batch(states, circuits, mode="auto", k_max=0, tile=0, launches=False,
 
 
 # ---- host-only diagnostics (no GPU) -----------------------------------------
-def host_plan(circ, dtype="c64", mode="auto", k_max=0, tile=0, from_zero=True, budget=0):
+def host_plan(circ, dtype="c64", mode="auto", k_max=0, tile=0, from_zero=True, budget=0, no_mfma=False):
     a = CircuitArgs(circ)
-    o = make_opts(mode, k_max, tile, budget=budget)
+    o = make_opts(mode, k_max, tile, no_mfma=no_mfma, budget=budget)
     sw = ctypes.c_int64()
     by = ctypes.c_double()
     mf = ctypes.c_int64()
@@ -344,9 +344,9 @@ def host_emulate(circ, psi: np.ndarray, dtype="c64", mode="auto", k_max=0, tile=
 
 
 def host_plan_describe(circ, dtype="c64", mode="auto", k_max=0, tile=0, from_zero=True,
-                       budget=0) -> str:
+                       budget=0, no_mfma=False) -> str:
     a = CircuitArgs(circ)
-    o = make_opts(mode, k_max, tile, budget=budget)
+    o = make_opts(mode, k_max, tile, no_mfma=no_mfma, budget=budget)
     buf = ctypes.create_string_buffer(1 << 20)
     check(lib().sv_host_plan_describe(a.ref, C64 if dtype == "c64" else C128, ctypes.byref(o),
                                       1 if from_zero else 0, buf, len(buf)))

@@ -93,6 +93,10 @@ def test_plan_sweep_counts_30q():
     assert spec["sweeps"] == circ.ngates - circ.n + 1
     assert reg["sweeps"] < 40 and f5["sweeps"] < 120
     assert f5["mfma_sweeps"] > 0
+    # without MFMA the same blocks run on the vector ALUs
+    f5v = sv.host_plan(circ, "c64", "fused", 5, no_mfma=True)
+    assert f5v["mfma_sweeps"] == 0 and f5v["sweeps"] == f5["sweeps"]
+    assert "mfma=1" not in sv.host_plan_describe(circ, "c64", "fused", 5, no_mfma=True)
     assert abs(plain["bytes"] - sum(
         (2 if g["kind"] != C.CZ else 1) * 8 * 2 ** 30 for g in circ.gates)) < 1
 
