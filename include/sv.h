@@ -218,6 +218,15 @@ sv_status sv_moments(sv_state *st, sv_stats *out);
  * k in 0..2^31.  Synchronises. */
 sv_status sv_sample(sv_state *st, int64_t k, uint64_t seed, uint64_t *out, int out_on_device);
 
+/* sv_moments and sv_sample in one read of the state: the statistic sums and
+ * the sampler's integer bucket weights come from the same pass.  The
+ * samples are bit-identical to those of sv_sample(st, k, seed, ...); the
+ * statistics equal those of sv_moments up to the order of the FP64 sums
+ * (workgroups of 2^16 amplitudes here).  k = 0 computes the statistics
+ * only; out (k entries, host or device) may then be NULL.  Synchronises. */
+sv_status sv_moments_sample(sv_state *st, sv_stats *stats, int64_t k, uint64_t seed, uint64_t *out,
+                            int out_on_device);
+
 /* The same sampler on an explicit distribution: probs (device, N doubles,
  * need not sum to 1), r64 (device, k random words), out (device, k).
  * N in 1..2^35.  Uses a scratch allocation of the library.  Synchronises. */

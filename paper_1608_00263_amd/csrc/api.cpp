@@ -449,6 +449,24 @@ sv_status sv_sample(sv_state *st, int64_t k, uint64_t seed, uint64_t *out, int o
     return SV_OK;
 }
 
+sv_status sv_moments_sample(sv_state *st, sv_stats *stats, int64_t k, uint64_t seed, uint64_t *out,
+                            int out_on_device) {
+    SV_TRY(check_state(st));
+    if (!stats) return fail(SV_EINVAL, "null statistics output");
+    if (k < 0 || k > ((int64_t)1 << 31)) return fail(SV_ERANGE, "sample count out of range");
+    if (k > 0 && !out) return fail(SV_EINVAL, "null output");
+    uint64_t *dout = out;
+    if (k > 0 && !out_on_device) {
+        SV_TRY(st->ws2.reserve((size_t)k * 8));
+        dout = (uint64_t *)st->ws2.ptr;
+    }
+    SV_TRY(run_stats_sample(st, st->data, stats, k, seed, dout));
+    if (k > 0 && !out_on_device)
+        SV_HIP(hipMemcpyAsync(out, dout, (size_t)k * 8, hipMemcpyDeviceToHost, st->stream));
+    SV_HIP(hipStreamSynchronize(st->stream));
+    return SV_OK;
+}
+
 sv_status sv_sample_from(const double *probs, uint64_t N, const uint64_t *r64, int64_t k, uint64_t *out,
                          void *hip_stream) {
     if (!probs || !r64 || (k > 0 && !out)) return fail(SV_EINVAL, "null pointer");

@@ -326,6 +326,8 @@ sv_status run_stats(sv_state *st, const void *psi, sv_stats *out);
 sv_status run_norm(sv_state *st, const void *psi, double *S);
 sv_status run_sample(sv_state *st, const void *psi, int64_t k, uint64_t seed,
                      uint64_t *dev_out);
+sv_status run_stats_sample(sv_state *st, const void *psi, sv_stats *stats, int64_t k, uint64_t seed,
+                           uint64_t *dev_out);
 sv_status run_sample_from(const double *probs, uint64_t N, const uint64_t *r64,
                           int64_t k, uint64_t *out, hipStream_t s);
 sv_status run_cross_entropy(sv_state *st, const void *psi, const uint64_t *dev_samples,

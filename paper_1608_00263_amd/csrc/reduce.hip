@@ -141,11 +141,10 @@ static sv_status stats_typed(sv_state *st, const void *psi, double *host16) {
     return SV_OK;
 }
 
-sv_status run_stats(sv_state *st, const void *psi, sv_stats *out) {
-    double r[16] = {0};
-    if (st->dt == SV_C64) SV_TRY((stats_typed<float, true>(st, psi, r)));
-    else SV_TRY((stats_typed<double, true>(st, psi, r)));
-    const double N = std::ldexp(1.0, st->n);
+// The normalised statistics from the combined sums r (S, sum p ln p,
+// sum ln p, sum u^k, zero count) of a 2^n-amplitude state.
+static void finish_stats(int n, const double *r, sv_stats *out) {
+    const double N = std::ldexp(1.0, n);
     const double S = r[0];
     const double lnS = std::log(S);
     out->norm = S;
@@ -157,6 +156,13 @@ sv_status run_stats(sv_state *st, const void *psi, sv_stats *out) {
         Sk *= S;
         out->moments[k] = r[3 + k] / N / Sk;
     }
+}
+
+sv_status run_stats(sv_state *st, const void *psi, sv_stats *out) {
+    double r[16] = {0};
+    if (st->dt == SV_C64) SV_TRY((stats_typed<float, true>(st, psi, r)));
+    else SV_TRY((stats_typed<double, true>(st, psi, r)));
+    finish_stats(st->n, r, out);
     return SV_OK;
 }
 
@@ -253,6 +259,68 @@ __global__ __launch_bounds__(RB) void k_bucket_weights(const S *__restrict__ src
         }
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int j = 0; j < nsub; j++) t += sh[j];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+// The statistics and the sampler's bucket weights in one read of the state:
+// workgroup b takes bucket b (2^bs amplitudes), each wavefront whole
+// sub-buckets of 2^sb amplitudes, as k_bucket_weights does; every amplitude
+// also enters this workgroup's row of statistic sums, as in k_stats.
+template <typename S>
+__global__ __launch_bounds__(RB) void k_stats_weights(const S *__restrict__ src, int bs, int sb, double Nd,
+                                                      double *__restrict__ part,
+                                                      unsigned long long *__restrict__ bsum,
+                                                      unsigned long long *__restrict__ subsum) {
+    __shared__ unsigned long long sh[64];
+    __shared__ double red[4 * NSTAT];
+    __shared__ unsigned zred[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nsub = 1 << (bs - sb);
+    const uint64_t slen = 1ull << sb;
+    double acc[NSTAT];
+#pragma unroll
+    for (int i = 0; i < NSTAT; i++) acc[i] = 0.0;
+    unsigned zeros = 0;
+    constexpr int UNR = 8;   // loads in flight per lane
+    for (int j = wave; j < nsub; j += RB / 64) {
+        const uint64_t start = ((uint64_t)blockIdx.x << bs) + ((uint64_t)j << sb);
+        unsigned long long w = 0;
+        const uint64_t main_end = slen - slen % (64 * UNR);
+        for (uint64_t e0 = lane; e0 < main_end; e0 += 64 * UNR) {
+            S buf[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; u++) buf[u] = src[start + e0 + (uint64_t)u * 64];
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                const double p = prob_of(buf[u]);
+                w += weight_of(p);
+                stat_add(acc, zeros, p, Nd);
+            }
+        }
+        for (uint64_t e = main_end + lane; e < slen; e += 64) {
+            const double p = prob_of(src[start + e]);
+            w += weight_of(p);
+            stat_add(acc, zeros, p, Nd);
+        }
+        w = wave_sum_u64(w);
+        if (lane == 0) {
+            subsum[(uint64_t)blockIdx.x * nsub + j] = w;
+            sh[j] = w;
+        }
+    }
+    block_sum<double, NSTAT>(acc, red);
+    zeros = wave_sum(zeros);
+    if (lane == 0) zred[wave] = zeros;
+    __syncthreads();
+    if (threadIdx.x < NSTAT) part[(uint64_t)blockIdx.x * 16 + threadIdx.x] = red[threadIdx.x];
+    if (threadIdx.x == NSTAT) {
+        const unsigned long long z = (unsigned long long)zred[0] + zred[1] + zred[2] + zred[3];
+        part[(uint64_t)blockIdx.x * 16 + NSTAT] = (double)z;
+    }
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (int j = 0; j < nsub; j++) t += sh[j];
@@ -366,10 +434,14 @@ __global__ __launch_bounds__(RB) void k_resolve(const S *__restrict__ src, int b
     }
 }
 
+// The sampler; with stats16 non-null (states only) the bucket weights come
+// from the fused statistics pass, whose 14 combined sums are copied to
+// stats16 (and k may be 0).
 template <typename S>
 static sv_status sample_impl(Workspace *ws, hipStream_t s, const S *src, int n, const uint64_t *words,
-                             uint64_t seed, int64_t k, uint64_t *dev_out) {
-    if (k <= 0) return SV_OK;
+                             uint64_t seed, int64_t k, uint64_t *dev_out, double *stats16 = nullptr) {
+    if (k <= 0 && !stats16) return SV_OK;
+    if (k < 0) k = 0;
     const int bs = n < 16 ? n : 16;
     const int sb = bs < SUB_BITS ? bs : SUB_BITS;
     const uint64_t nb = 1ull << (n - bs);
@@ -378,6 +450,7 @@ static sv_status sample_impl(Workspace *ws, hipStream_t s, const S *src, int n, 
     auto take = [&](size_t bytes) { size_t o = need; need += (bytes + 255) & ~(size_t)255; return o; };
     size_t o_bsum = take(nb * 8), o_off = take((nb + 1) * 8), o_sub = take(nsubs * 8),
            o_tb = take((size_t)k * 4), o_tl = take((size_t)k * 8);
+    const size_t o_part = stats16 ? take(nb * 16 * 8) : 0, o_res = stats16 ? take(16 * 8) : 0;
     SV_TRY(ws->reserve(need));
     uint8_t *w = (uint8_t *)ws->ptr;
     auto *bsum = (unsigned long long *)(w + o_bsum);
@@ -385,7 +458,20 @@ static sv_status sample_impl(Workspace *ws, hipStream_t s, const S *src, int n, 
     auto *sub = (unsigned long long *)(w + o_sub);
     auto *tb = (uint32_t *)(w + o_tb);
     auto *tl = (unsigned long long *)(w + o_tl);
-    hipLaunchKernelGGL((k_bucket_weights<S>), dim3((unsigned)nb), dim3(RB), 0, s, src, bs, sb, bsum, sub);
+    if (stats16) {
+        double *part = (double *)(w + o_part), *res = (double *)(w + o_res);
+        hipLaunchKernelGGL((k_stats_weights<S>), dim3((unsigned)nb), dim3(RB), 0, s, src, bs, sb,
+                           std::ldexp(1.0, n), part, bsum, sub);
+        hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, s, part, (int)nb, NSTAT + 1, res);
+        SV_HIP(hipGetLastError());
+        SV_HIP(hipMemcpyAsync(stats16, res, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (k == 0) {
+            SV_HIP(hipStreamSynchronize(s));
+            return SV_OK;
+        }
+    } else {
+        hipLaunchKernelGGL((k_bucket_weights<S>), dim3((unsigned)nb), dim3(RB), 0, s, src, bs, sb, bsum, sub);
+    }
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, bsum, nb, off);
     unsigned long long W = 0;
     SV_HIP(hipMemcpyAsync(&W, off + nb, 8, hipMemcpyDeviceToHost, s));
@@ -405,6 +491,19 @@ sv_status run_sample(sv_state *st, const void *psi, int64_t k, uint64_t seed, ui
                                        seed, k, dev_out);
     return sample_impl<cpx<double>>(&st->ws, st->stream, (const cpx<double> *)psi, st->n, nullptr,
                                     seed, k, dev_out);
+}
+
+sv_status run_stats_sample(sv_state *st, const void *psi, sv_stats *stats, int64_t k, uint64_t seed,
+                           uint64_t *dev_out) {
+    double r[16] = {0};
+    if (st->dt == SV_C64)
+        SV_TRY(sample_impl<cpx<float>>(&st->ws, st->stream, (const cpx<float> *)psi, st->n, nullptr, seed, k,
+                                       dev_out, r));
+    else
+        SV_TRY(sample_impl<cpx<double>>(&st->ws, st->stream, (const cpx<double> *)psi, st->n, nullptr, seed, k,
+                                        dev_out, r));
+    finish_stats(st->n, r, stats);
+    return SV_OK;
 }
 
 sv_status run_sample_from(const double *probs, uint64_t N, const uint64_t *r64, int64_t k,

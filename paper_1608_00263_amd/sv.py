@@ -78,6 +78,8 @@ EXPORTS = {
     "sv_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sv_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p,
                                  ctypes.c_int]),
+    "sv_moments_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
+                                         ctypes.c_void_p, ctypes.c_int]),
     "sv_sample_from": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                       ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "sv_cross_entropy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
@@ -258,6 +260,13 @@ class State:
         out = np.zeros(max(k, 1), dtype=np.uint64)
         check(lib().sv_sample(self.h, k, ctypes.c_uint64(seed), _ptr(out), 0))
         return out[:k]
+
+    def moments_and_sample(self, k: int, seed: int):
+        """(moments(), sample(k, seed)) from one read of the state."""
+        s = Stats()
+        out = np.zeros(max(k, 1), dtype=np.uint64)
+        check(lib().sv_moments_sample(self.h, ctypes.byref(s), k, ctypes.c_uint64(seed), _ptr(out), 0))
+        return s.as_dict(), out[:k]
 
     def cross_entropy(self, samples: np.ndarray, norm=None):
         """(ce, delta_h, zero_samples) of the samples; norm, when given, is

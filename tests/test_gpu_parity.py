@@ -204,6 +204,34 @@ def test_sample_state_bit_exact(dtype):
     st.close()
 
 
+@pytest.mark.parametrize("dtype,n,zeros,k", [("c64", 4, 3, 50), ("c64", 9, 0, 1000), ("c128", 12, 100, 5000),
+                                              ("c64", 17, 2000, 20000), ("c128", 18, 0, 20000),
+                                              ("c64", 20, 0, 0)])
+def test_moments_and_sample_one_pass(dtype, n, zeros, k):
+    # statistics and samples from one read of the state: the samples are
+    # those of the sampler alone and of the oracle, bit for bit; the
+    # statistics those of the oracle (and of the statistics pass alone)
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    psi = C.random_state(n, 60 + n, dtype=npdt)
+    if zeros:
+        psi[np.random.default_rng(n).choice(1 << n, zeros, replace=False)] = 0
+    st = sv.State(n, dtype, tensor=torch.from_numpy(psi).to("cuda"))
+    m, xs = st.moments_and_sample(k, 4321)
+    assert xs.size == k
+    if k:
+        np.testing.assert_array_equal(xs, st.sample(k, 4321))
+        np.testing.assert_array_equal(xs, oracle.sample(oracle.probs(psi), k, 4321))
+    want = oracle.stats(oracle.probs(psi))
+    alone = st.moments()
+    assert m["zero_count"] == want["zero_count"] == alone["zero_count"] == zeros
+    keys = ("norm", "entropy") if zeros else ("norm", "entropy", "unif_ce")
+    for key in keys:
+        assert abs(m[key] - want[key]) <= 1e-12 * max(1, abs(want[key])), key
+        assert abs(m[key] - alone[key]) <= 1e-12 * max(1, abs(want[key])), key
+    np.testing.assert_allclose(m["moments"], want["moments"], rtol=1e-11)
+    st.close()
+
+
 def test_sample_point_mass():
     st = sv.State(10, "c64")
     st.reset()
