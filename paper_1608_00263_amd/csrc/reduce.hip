@@ -267,12 +267,14 @@ __global__ __launch_bounds__(RB) void k_bucket_weights(const S *__restrict__ src
 }
 
 // The statistics and the sampler's bucket weights in one read of the state:
-// workgroup b takes bucket b (2^bs amplitudes), each wavefront whole
-// sub-buckets of 2^sb amplitudes, as k_bucket_weights does; every amplitude
-// also enters this workgroup's row of statistic sums, as in k_stats.
+// workgroup g takes buckets g, g + G, ... (2^bs amplitudes each; G = the
+// grid size, at most 2048 so that few statistic rows remain to combine),
+// each wavefront whole sub-buckets of 2^sb amplitudes, as k_bucket_weights
+// does; every amplitude also enters this workgroup's row of statistic sums,
+// as in k_stats.
 template <typename S>
-__global__ __launch_bounds__(RB) void k_stats_weights(const S *__restrict__ src, int bs, int sb, double Nd,
-                                                      double *__restrict__ part,
+__global__ __launch_bounds__(RB) void k_stats_weights(const S *__restrict__ src, int bs, int sb, uint64_t nbk,
+                                                      double Nd, double *__restrict__ part,
                                                       unsigned long long *__restrict__ bsum,
                                                       unsigned long long *__restrict__ subsum) {
     __shared__ unsigned long long sh[64];
@@ -286,8 +288,9 @@ __global__ __launch_bounds__(RB) void k_stats_weights(const S *__restrict__ src,
     for (int i = 0; i < NSTAT; i++) acc[i] = 0.0;
     unsigned zeros = 0;
     constexpr int UNR = 8;   // loads in flight per lane
-    for (int j = wave; j < nsub; j += RB / 64) {
-        const uint64_t start = ((uint64_t)blockIdx.x << bs) + ((uint64_t)j << sb);
+    for (uint64_t b = blockIdx.x; b < nbk; b += gridDim.x) {
+      for (int j = wave; j < nsub; j += RB / 64) {
+        const uint64_t start = (b << bs) + ((uint64_t)j << sb);
         unsigned long long w = 0;
         const uint64_t main_end = slen - slen % (64 * UNR);
         for (uint64_t e0 = lane; e0 < main_end; e0 += 64 * UNR) {
@@ -308,9 +311,17 @@ __global__ __launch_bounds__(RB) void k_stats_weights(const S *__restrict__ src,
         }
         w = wave_sum_u64(w);
         if (lane == 0) {
-            subsum[(uint64_t)blockIdx.x * nsub + j] = w;
+            subsum[b * nsub + j] = w;
             sh[j] = w;
         }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+          unsigned long long t = 0;
+          for (int j = 0; j < nsub; j++) t += sh[j];
+          bsum[b] = t;
+      }
+      __syncthreads();   // sh is reused by the next bucket
     }
     block_sum<double, NSTAT>(acc, red);
     zeros = wave_sum(zeros);
@@ -320,11 +331,6 @@ __global__ __launch_bounds__(RB) void k_stats_weights(const S *__restrict__ src,
     if (threadIdx.x == NSTAT) {
         const unsigned long long z = (unsigned long long)zred[0] + zred[1] + zred[2] + zred[3];
         part[(uint64_t)blockIdx.x * 16 + NSTAT] = (double)z;
-    }
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int j = 0; j < nsub; j++) t += sh[j];
-        bsum[blockIdx.x] = t;
     }
 }
 
@@ -450,7 +456,8 @@ static sv_status sample_impl(Workspace *ws, hipStream_t s, const S *src, int n, 
     auto take = [&](size_t bytes) { size_t o = need; need += (bytes + 255) & ~(size_t)255; return o; };
     size_t o_bsum = take(nb * 8), o_off = take((nb + 1) * 8), o_sub = take(nsubs * 8),
            o_tb = take((size_t)k * 4), o_tl = take((size_t)k * 8);
-    const size_t o_part = stats16 ? take(nb * 16 * 8) : 0, o_res = stats16 ? take(16 * 8) : 0;
+    const uint64_t ng = nb < 2048 ? nb : 2048;   // workgroups of the fused statistics pass
+    const size_t o_part = stats16 ? take(ng * 16 * 8) : 0, o_res = stats16 ? take(16 * 8) : 0;
     SV_TRY(ws->reserve(need));
     uint8_t *w = (uint8_t *)ws->ptr;
     auto *bsum = (unsigned long long *)(w + o_bsum);
@@ -460,9 +467,9 @@ static sv_status sample_impl(Workspace *ws, hipStream_t s, const S *src, int n, 
     auto *tl = (unsigned long long *)(w + o_tl);
     if (stats16) {
         double *part = (double *)(w + o_part), *res = (double *)(w + o_res);
-        hipLaunchKernelGGL((k_stats_weights<S>), dim3((unsigned)nb), dim3(RB), 0, s, src, bs, sb,
+        hipLaunchKernelGGL((k_stats_weights<S>), dim3((unsigned)ng), dim3(RB), 0, s, src, bs, sb, nb,
                            std::ldexp(1.0, n), part, bsum, sub);
-        hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, s, part, (int)nb, NSTAT + 1, res);
+        hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, s, part, (int)ng, NSTAT + 1, res);
         SV_HIP(hipGetLastError());
         SV_HIP(hipMemcpyAsync(stats16, res, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
         if (k == 0) {
