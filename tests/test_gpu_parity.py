@@ -232,6 +232,23 @@ def test_moments_and_sample_one_pass(dtype, n, zeros, k):
     st.close()
 
 
+def test_moments_sample_device_output_and_errors():
+    import ctypes
+    n, k = 14, 3000
+    psi = C.random_state(n, 71, dtype=np.complex64)
+    st = sv.State(n, "c64", tensor=torch.from_numpy(psi).to("cuda"))
+    out = torch.zeros(k, dtype=torch.int64, device="cuda")
+    s = sv.Stats()
+    L = sv.lib()
+    assert L.sv_moments_sample(st.h, ctypes.byref(s), k, ctypes.c_uint64(99), ctypes.c_void_p(out.data_ptr()), 1) == 0
+    np.testing.assert_array_equal(out.cpu().numpy().view(np.uint64), st.sample(k, 99))
+    assert abs(s.as_dict()["entropy"] - st.moments()["entropy"]) < 1e-12 * n
+    assert L.sv_moments_sample(st.h, None, k, ctypes.c_uint64(99), ctypes.c_void_p(out.data_ptr()), 1) == sv.SV_EINVAL
+    assert L.sv_moments_sample(st.h, ctypes.byref(s), -1, ctypes.c_uint64(99), None, 0) == sv.SV_ERANGE
+    assert L.sv_moments_sample(st.h, ctypes.byref(s), k, ctypes.c_uint64(99), None, 0) == sv.SV_EINVAL
+    st.close()
+
+
 def test_sample_point_mass():
     st = sv.State(10, "c64")
     st.reset()
