@@ -125,6 +125,40 @@ def test_c2_register_tiles_vs_per_gate_c128(st30):
     torch.cuda.empty_cache()
 
 
+def test_c3_full_ensemble_subset():
+    # the 512-instance ensemble of the benchmark (67 GB of complex64 states)
+    # in one call; every 16th instance against a single-state run of the same
+    # circuit, and its 20-qubit ones against the FP64 reference
+    import oracle
+    circs = C.make_ensemble(512)
+    print("ensemble: allocating 512 states", flush=True)
+    states = [sv.State(c.n, "c64") for c in circs]
+    res = sv.apply_batch(states, circs)
+    one = {}
+    for i in range(0, 512, 16):
+        c = circs[i]
+        ref_gpu = sv.State(c.n, "c64")
+        ref_gpu.apply(c, "regtile", from_zero=True)
+        d = float(torch.linalg.vector_norm(states[i].tensor - ref_gpu.tensor))
+        assert d <= 1e-5, (i, d)
+        m = ref_gpu.moments()
+        assert abs(res[i]["entropy"] - m["entropy"]) < 1e-6, i
+        np.testing.assert_allclose(res[i]["moments"][:5], m["moments"][:5], rtol=1e-5)
+        ref_gpu.close()
+        if c.n == 20:
+            print("ensemble instance %d: FP64 reference" % i, flush=True)
+            ref = oracle.apply_circuit(c)
+            assert np.linalg.norm(states[i].amplitudes() - ref) <= 1e-4, i
+            want = oracle.stats(oracle.probs(ref))
+            assert abs(res[i]["entropy"] - want["entropy"]) < 1e-4, i
+            one[i] = True
+    assert len(one) == 9
+    for st in states:
+        st.close()
+    del states
+    torch.cuda.empty_cache()
+
+
 def test_c5_clifford_variant_vs_tableau(st35):
     circ = C.make_circuit(5, 7, 40, seed=5, clifford=True)
     print("clifford variant: %d gates" % circ.ngates, flush=True)
