@@ -159,6 +159,37 @@ def test_c3_full_ensemble_subset():
     torch.cuda.empty_cache()
 
 
+def test_c4_adjoint_full_size():
+    # the benchmark's gradient workload (5x5 grid, 25 qubits, depth 30, 216
+    # parameters, 10^4 samples of the theta = 0 circuit): the complex64
+    # adjoint against the complex128 one over every parameter, and the
+    # complex128 one against central differences of the loss on 16 seeded
+    # parameters (h = 1e-4: truncation near 1e-8, rounding near 1e-10)
+    circ = C.make_circuit(5, 5, 30, seed=4, parametrise=True, theta_seed=4004, theta_std=0.05)
+    st = sv.State(25, "c64")
+    st.apply(circ.with_theta(np.zeros(circ.nparams)), "regtile", 0, 6, from_zero=True)
+    xs = st.sample(10 ** 4, 1004)
+    loss64, g64 = st.backward(circ, xs)
+    st.close()
+    s128 = sv.State(25, "c128")
+    loss128, g128 = s128.backward(circ, xs)
+    assert abs(loss64 - loss128) < 1e-4
+    assert np.abs(g64 - g128).max() < 1e-4
+    assert np.linalg.norm(g64 - g128) <= 1e-3 * np.linalg.norm(g128)
+    h = 1e-4
+    for g in np.random.default_rng(16).choice(circ.nparams, 16, replace=False):
+        vals = []
+        for sgn in (1.0, -1.0):
+            th = circ.theta.copy()
+            th[g] += sgn * h
+            s128.apply(circ.with_theta(th), "regtile", 0, 5, from_zero=True)
+            vals.append(s128.cross_entropy(xs)[0])
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g128[g]) < 1e-6 * max(1.0, abs(g128[g])), (int(g), fd, g128[g])
+    s128.close()
+    torch.cuda.empty_cache()
+
+
 def test_c5_clifford_variant_vs_tableau(st35):
     circ = C.make_circuit(5, 7, 40, seed=5, clifford=True)
     print("clifford variant: %d gates" % circ.ngates, flush=True)
