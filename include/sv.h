@@ -253,7 +253,10 @@ sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k, dou
  * it must hold U(theta)|0...0> already (as left by sv_apply_circuit of the
  * same circuit), the forward pass is skipped, and checkpoint_c must be 0.
  * On return its contents are unspecified (the forward state has been
- * uncomputed).  loss gets L(theta).  Uses device
+ * uncomputed).  loss gets L(theta).  The reverse sweeps are register tiles:
+ * opts->tile_qubits register qubits (0 = default 5 complex64 / 3
+ * complex128; clamped to 1..5 / 1..4 and to at most n - 8) under
+ * opts->sweep_budget (as for sv_apply_circuit).  Uses device
  * scratch of one extra state plus the checkpoints.  SV_EINVAL if a
  * parametrised gate is not a rotation; SV_ESTATE if a sample has p = 0;
  * SV_ERANGE for n < 8. */
