@@ -279,24 +279,29 @@ def mode_timings(sv, C, circ, torch):
                  ("tiled", 4, 13 if dtype == "c64" else 12, False)]
         if dtype == "c64":
             modes += [("fused", 4, 0, True), ("fused", 5, 0, True), ("regtile", 0, 4, False),
-                      ("regtile", 0, 5, False), ("regtile", 0, 6, False)]
+                      ("regtile", 0, 5, False), ("regtile", 0, 6, False),
+                      # few gates per sweep: more sweeps, each close to streaming
+                      ("regtile_b60", 0, 6, False)]
         else:
             modes += [("regtile", 0, 3, False), ("regtile", 0, 4, False), ("regtile", 0, 5, False)]
         modes += [("auto", 0, 0, False)]
         for mode, k, t, nomf in modes:
-            st.apply(circ, mode, k, t, args=args, from_zero=True, no_mfma=nomf)   # plan + warm / tune
+            budget = 60 if mode.endswith("_b60") else 0
+            mode = mode.replace("_b60", "")
+            st.apply(circ, mode, k, t, args=args, from_zero=True, no_mfma=nomf, budget=budget)   # plan + warm / tune
             if mode == "auto":
                 for _ in range(8):
                     st.apply(circ, mode, k, t, args=args, from_zero=True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            st.apply(circ, mode, k, t, args=args, from_zero=True, no_mfma=nomf)
+            st.apply(circ, mode, k, t, args=args, from_zero=True, no_mfma=nomf, budget=budget)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            sw, by = st.plan_info(circ, mode, k, t, no_mfma=nomf, from_zero=True)
-            key = "%s_%s%s%s" % (dtype, mode, ("_k%d" % k if k else "") + ("_t%d" % t if t else ""),
-                                 "_valu" if nomf else "")
-            res[key] = {"s": round(dt, 4), "sweeps": sw, "GBps": round(by / dt / 1e9, 1)}
+            sw, by = st.plan_info(circ, mode, k, t, no_mfma=nomf, from_zero=True, budget=budget)
+            key = "%s_%s%s%s%s" % (dtype, mode, ("_k%d" % k if k else "") + ("_t%d" % t if t else ""),
+                                   "_valu" if nomf else "", "_b%d" % budget if budget else "")
+            res[key] = {"s": round(dt, 4), "sweeps": sw, "GBps": round(by / dt / 1e9, 1),
+                        "frac_of_peak": round(by / dt / 1e9 / PEAK_HBM_GBPS, 4)}
             if mode in ("fused", "tiled"):
                 tot, mf = dense_block_flops(sv, circ, dtype, mode, k, t, nomf)
                 res[key]["dense_TFLOPs"] = round(tot / dt / 1e12, 2)
