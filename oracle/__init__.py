@@ -141,6 +141,8 @@ def cross_entropy(p: np.ndarray, samples: np.ndarray):
     ce = ctypes.c_double()
     dh = ctypes.c_double()
     z = lib().orc_cross_entropy(n, _ptr(p), _ptr(x), x.size, ctypes.byref(ce), ctypes.byref(dh))
+    if z < 0:
+        raise ValueError("a sample is not an %d-bit string" % n)
     return ce.value, dh.value, int(z)
 
 

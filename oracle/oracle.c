@@ -342,6 +342,9 @@ static uint64_t weight(double p) {
     return (uint64_t)ldexp(p, 62);
 }
 
+/* Returns 0, or -1 (no memory), -2 (a p_j negative, NaN or >= 4, whose
+ * weight does not fit), -3 (every weight is 0), -4 (the total W does not
+ * fit in 64 bits: the weights must sum below 2^64, i.e. sum p < 4). */
 int orc_sample_from_words(uint64_t N, const double *p, const uint64_t *r,
                           int64_t k, uint64_t *out) {
     uint64_t *C = (uint64_t *)malloc(sizeof(uint64_t) * N);
@@ -349,7 +352,9 @@ int orc_sample_from_words(uint64_t N, const double *p, const uint64_t *r,
     uint64_t run = 0;
     for (uint64_t j = 0; j < N; j++) {
         if (!(p[j] >= 0.0) || p[j] >= 4.0) { free(C); return -2; }
-        run += weight(p[j]);
+        const uint64_t w = weight(p[j]);
+        if (run + w < run) { free(C); return -4; }
+        run += w;
         C[j] = run;
     }
     const uint64_t W = run;
@@ -382,16 +387,20 @@ int orc_sample(uint64_t N, const double *p, uint64_t seed, int64_t k, uint64_t *
  *   CE = ln S - (1/m) sum_i ln p(x_i),  dH = ln N + gamma - CE,
  * with S = sum_j p_j (compensated as in orc_stats).  A sample with
  * p(x_i) = 0 makes CE = +inf; the number of such samples is returned.
+ * A sample is an n-bit string (Sec. II): x_i >= 2^n has no probability,
+ * and the call returns -1 without output.
  * ------------------------------------------------------------------- */
 int64_t orc_cross_entropy(int n, const double *p, const uint64_t *x, int64_t m,
                           double *ce, double *dh) {
     const int64_t N = (int64_t)1 << n;
+    for (int64_t i = 0; i < m; i++)
+        if (x[i] >= (uint64_t)N) return -1;
     double st[14];
     orc_stats(n, p, st);
     nsum acc = { 0, 0 };
     int64_t zero = 0;
     for (int64_t i = 0; i < m; i++) {
-        double pi = p[x[i] & (uint64_t)(N - 1)];
+        double pi = p[x[i]];
         if (pi > 0.0) nadd(&acc, log(pi)); else zero++;
     }
     const double euler_gamma = 0.57721566490153286061;
@@ -435,6 +444,8 @@ int orc_adjoint(int n, const int32_t *gates, int64_t ngates, const double *theta
                 int nparams, const double *mats, int nmats, const uint64_t *x,
                 int64_t m, double *loss, double *grad) {
     const int64_t N = (int64_t)1 << n;
+    for (int64_t i = 0; i < m; i++)
+        if (x[i] >= (uint64_t)N) return -5;   /* not an n-bit string */
     cx *phi = (cx *)malloc(sizeof(cx) * N);
     cx *mu = (cx *)calloc((size_t)N, sizeof(cx));
     if (!phi || !mu) { free(phi); free(mu); return -1; }
@@ -443,7 +454,7 @@ int orc_adjoint(int n, const int32_t *gates, int64_t ngates, const double *theta
     if (rc) { free(phi); free(mu); return rc; }
     nsum l = { 0, 0 };
     for (int64_t i = 0; i < m; i++) {
-        int64_t xi = (int64_t)(x[i] & (uint64_t)(N - 1));
+        int64_t xi = (int64_t)x[i];
         double re = phi[xi].re, im = phi[xi].im;
         double px = re * re + im * im;
         if (!(px > 0.0)) { free(phi); free(mu); return -2; }

@@ -355,6 +355,33 @@ def test_stats_bruteforce_small():
 
 
 # --------------------------------------------------------------------------
+# probabilities (Sec. II: p(x) = |<x|psi>|^2)
+# --------------------------------------------------------------------------
+def test_probs_c64_exact_products():
+    # complex64 amplitudes: re^2 and im^2 have at most 48 significant bits, so
+    # both products are exact in FP64 and the only rounding is the sum; the
+    # result must equal the FP64 formula on the widened amplitudes bit for bit
+    psi = C.random_state(13, 90, dtype=np.complex64)
+    psi[5] = 0
+    psi[6] = np.complex64(np.float32(np.finfo(np.float32).tiny) + 0j)
+    got = oracle.probs(psi)
+    wide = oracle.probs(psi.astype(np.complex128))
+    np.testing.assert_array_equal(got, wide)
+    assert got[5] == 0.0 and got[6] == 2.0 ** -252
+    # hand values: (3/4 + i/2) -> 9/16 + 1/4 = 13/16 exactly; re = 1 + 2^-23,
+    # im = 2^-12 -> 1 + 2^-22 + 2^-24 + 2^-46 exactly (a single-precision
+    # product would drop the 2^-46 term of re^2)
+    h = np.array([0.75 + 0.5j, (1.0 + 2.0 ** -23) + 2.0 ** -12 * 1j, -3.0 - 4.0j, 1e-20j],
+                 dtype=np.complex64)
+    ph = oracle.probs(h)
+    assert ph[0] == 13.0 / 16.0
+    assert ph[1] == 1.0 + 2.0 ** -22 + 2.0 ** -24 + 2.0 ** -46
+    assert ph[2] == 25.0
+    f = float(np.float32(1e-20))
+    assert ph[3] == f * f
+
+
+# --------------------------------------------------------------------------
 # sampler
 # --------------------------------------------------------------------------
 def test_sampler_two_point_closed_form():
@@ -377,6 +404,18 @@ def test_sampler_definition_small():
         assert j == xi
     assert all(p[int(v)] > 0 for v in x)
     np.testing.assert_array_equal(oracle.sample(p, 3000, 4), x)
+
+
+def test_sampler_rejects_weights_that_do_not_fit():
+    # weights floor(p 2^62) must sum below 2^64 (sum p < 4); a p >= 4, a
+    # negative p or a NaN has no 64-bit weight
+    words = C.splitmix64_words(5, 10)
+    oracle.sample_from_words(np.array([1.99, 1.99]), words)
+    for bad in ([2.0, 2.0], [3.0, 0.5, 0.75], [4.0], [-0.5, 1.0], [float("nan"), 1.0]):
+        with pytest.raises(ValueError):
+            oracle.sample_from_words(np.array(bad), words)
+    with pytest.raises(ValueError):
+        oracle.sample_from_words(np.zeros(8), words)
 
 
 def test_sampler_frequencies():
@@ -445,6 +484,11 @@ def test_cross_entropy_closed_forms(c1_probs):
     pz[int(xs[0])] = 0.0
     ce, dh, z = oracle.cross_entropy(pz, xs)
     assert ce == math.inf and z >= 1
+    # a sample is an n-bit string: an index >= 2^n is rejected, not wrapped
+    bad = xs.copy()
+    bad[3] = np.uint64(p.size)
+    with pytest.raises(ValueError):
+        oracle.cross_entropy(p, bad)
 
 
 # --------------------------------------------------------------------------
@@ -474,6 +518,10 @@ def test_adjoint_parameter_shift():
         dp = 0.5 * (pp[xi] - pm[xi])
         shift[g] = -np.mean(dp / p[xi])
     np.testing.assert_allclose(grad, shift, atol=1e-10 * max(1.0, np.abs(shift).max()))
+    bad = xs.copy()
+    bad[0] = np.uint64(1 << circ.n)
+    with pytest.raises(ValueError):
+        oracle.adjoint(circ, bad)
 
 
 def test_adjoint_central_difference():
