@@ -155,7 +155,11 @@ sv_status sv_attach(int n, sv_dtype dt, void *dev_ptr, void *hip_stream, sv_stat
 
 sv_status sv_free(sv_state *st);
 
-/* Set the state to |0...0> (Sec. II, psi_0). */
+/* Set the state to |0...0> (Sec. II, psi_0).  For a buffer the library
+ * owns (sv_alloc) the next sv_apply_circuit may take the contents as known
+ * to be |0...0> (and generate a leading Hadamard layer instead of reading
+ * the state); an attached buffer is always read, since its owner may have
+ * written it in between. */
 sv_status sv_reset(sv_state *st);
 
 /* Device pointer of the amplitudes (interleaved re, im). */
@@ -200,9 +204,12 @@ enum {
 sv_status sv_apply_circuit_timed(sv_state *st, const sv_circuit *c, const sv_opts *opts, int64_t cap,
                                  float *op_ms, int32_t *op_kind, double *op_bytes, int64_t *nops);
 
-/* p(x) = re^2 + im^2 for x in [begin, begin + count), written to dev_out
- * (device) as double (out_f64 = 1) or float.  For SV_C64 the two products
- * are exact in double.  SV_ERANGE if the range leaves [0, 2^n). */
+/* Output probabilities p_U(x) = |<x|psi>|^2 (Sec. II) as re^2 + im^2, for
+ * x in [begin, begin + count), written to dev_out (device, count entries,
+ * caller-owned) as double (out_f64 = 1) or float (out_f64 = 0).  For
+ * SV_C64 both products are exact in double and the sum is rounded once.
+ * Asynchronous on the handle's stream.  SV_ERANGE if the range leaves
+ * [0, 2^n); SV_EINVAL for a null dev_out with count > 0. */
 sv_status sv_probs(sv_state *st, uint64_t begin, uint64_t count, int out_f64, void *dev_out);
 
 /* Output statistics of the current state (one FP64 pass, compensated,
@@ -228,8 +235,13 @@ sv_status sv_moments_sample(sv_state *st, sv_stats *stats, int64_t k, uint64_t s
                             int out_on_device);
 
 /* The same sampler on an explicit distribution: probs (device, N doubles,
- * need not sum to 1), r64 (device, k random words), out (device, k).
- * N in 1..2^35.  Uses a scratch allocation of the library.  Synchronises. */
+ * need not sum to 1), r64 (device, k random words used as the r_i above),
+ * out (device, k entries, caller-owned).  N is any length in 1..2^35 (else
+ * SV_ERANGE).  Every p must be finite, >= 0 and below 4, so that its weight
+ * floor(p 2^62) fits 64 bits (else SV_EINVAL), and the weights must sum
+ * below 2^64, i.e. sum p < 4 up to the floors (else SV_ERANGE); SV_ESTATE
+ * when every weight is 0 and k > 0.  The check is exact (integer sums).
+ * Uses a scratch allocation of the library.  Synchronises. */
 sv_status sv_sample_from(const double *probs, uint64_t N, const uint64_t *r64,
                          int64_t k, uint64_t *out, void *hip_stream);
 
@@ -238,7 +250,9 @@ sv_status sv_sample_from(const double *probs, uint64_t N, const uint64_t *r64,
  * over k samples (host array); S = sum_x p(x).  norm > 0 is taken as S (the
  * norm sv_moments returned for the same state, which saves a pass over the
  * state); norm <= 0 computes it.  ce = +inf when some p(x_i) = 0;
- * *zero_samples (may be NULL) gets their number.  Synchronises. */
+ * *zero_samples (may be NULL) gets their number.  Samples are n-bit
+ * strings: SV_ERANGE (before any device work) if some x_i >= 2^n.
+ * Synchronises. */
 sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k, double norm,
                            double *ce, double *delta_h, int64_t *zero_samples);
 
@@ -259,7 +273,8 @@ sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k, dou
  * opts->sweep_budget (as for sv_apply_circuit).  Uses device
  * scratch of one extra state plus the checkpoints.  SV_EINVAL if a
  * parametrised gate is not a rotation; SV_ESTATE if a sample has p = 0;
- * SV_ERANGE for n < 8. */
+ * SV_ERANGE for n < 8 or a sample x_i >= 2^n (checked before any device
+ * work). */
 sv_status sv_backward(sv_state *st, const sv_circuit *c, const sv_opts *opts,
                       const uint64_t *samples, int64_t k, int checkpoint_c,
                       double *loss, double *grad);

@@ -18,14 +18,29 @@ import torch
 from . import sv
 
 
+class _Stamp:
+    """Which forward's output state the module's GPU state holds: the
+    generation number of that forward, or None once anything else (a later
+    forward's backward, an uncomputation) has changed the contents."""
+
+    def __init__(self):
+        self.last = 0        # generation of the most recent forward
+        self.ready = None    # generation whose output the state holds
+
+
 class _CircuitCrossEntropy(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, theta, circ, state, samples, checkpoint_c):
+    def forward(ctx, theta, circ, state, samples, checkpoint_c, stamp):
         c = circ.with_theta(theta.detach().to("cpu", torch.float64).numpy())
+        stamp.last += 1
+        stamp.ready = None
         state.apply(c, "auto", from_zero=True)
         ce, _, zeros = state.cross_entropy(samples)
         if zeros:
             raise sv.SVError(sv.SV_ESTATE, "a sample has probability 0 under the circuit")
+        stamp.ready = stamp.last
+        ctx.gen = stamp.last
+        ctx.stamp = stamp
         ctx.circ = c
         ctx.state = state
         ctx.samples = samples
@@ -35,12 +50,16 @@ class _CircuitCrossEntropy(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        ready = ctx.checkpoint_c == 0
+        # the forward state is reused only while the handle still holds this
+        # forward's output (no later forward, no earlier backward, which
+        # uncomputes it); otherwise the backward recomputes it from |0..0>
+        ready = ctx.checkpoint_c == 0 and ctx.stamp.ready == ctx.gen
+        ctx.stamp.ready = None
         _, grad = ctx.state.backward(ctx.circ, ctx.samples, checkpoint_c=ctx.checkpoint_c,
                                      state_ready=ready)
         dtype, device = ctx.theta_meta
         gt = torch.from_numpy(np.asarray(grad, dtype=np.float64)).to(device=device, dtype=dtype)
-        return g.to(device=device, dtype=dtype) * gt, None, None, None, None
+        return g.to(device=device, dtype=dtype) * gt, None, None, None, None, None
 
 
 class CircuitCrossEntropy(torch.nn.Module):
@@ -48,8 +67,10 @@ class CircuitCrossEntropy(torch.nn.Module):
 
     circ: a parametrised circuit (its theta is replaced by the input);
     samples: uint64 bit-strings; checkpoint_c: 0 reuses the forward state for
-    the backward pass, c > 0 recomputes it with a state copy kept every c
-    cycles.  The module owns one GPU state of the circuit's size.
+    the backward pass (while the module's state still holds that forward's
+    output; after another forward or backward it is recomputed), c > 0
+    recomputes it with a state copy kept every c cycles.  The module owns one
+    GPU state of the circuit's size.
     """
 
     def __init__(self, circ, samples, dtype: str = "c64", checkpoint_c: int = 0):
@@ -58,12 +79,14 @@ class CircuitCrossEntropy(torch.nn.Module):
         self.samples = np.ascontiguousarray(samples, dtype=np.uint64)
         self.checkpoint_c = int(checkpoint_c)
         self.state = sv.State(circ.n, dtype)
+        self._stamp = _Stamp()
 
     def forward(self, theta: torch.Tensor) -> torch.Tensor:
         if theta.numel() != self.circ.nparams:
             raise ValueError("theta has %d entries, the circuit %d parameters"
                              % (theta.numel(), self.circ.nparams))
-        return _CircuitCrossEntropy.apply(theta, self.circ, self.state, self.samples, self.checkpoint_c)
+        return _CircuitCrossEntropy.apply(theta, self.circ, self.state, self.samples, self.checkpoint_c,
+                                          self._stamp)
 
     def close(self):
         self.state.close()

@@ -431,13 +431,14 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
 }
 
 // mu = 0, then mu_x += psi_x / (m p_x) for every sample x (repeated samples
-// add identical terms, so the sum does not depend on their order)
+// add identical terms, so the sum does not depend on their order); the
+// samples are n-bit strings (checked on the host)
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_lambda(const cplx<T> *__restrict__ psi, cplx<T> *__restrict__ mu,
-                                                  const uint64_t *__restrict__ x, int64_t m, uint64_t mask) {
+                                                  const uint64_t *__restrict__ x, int64_t m) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= m) return;
-    const uint64_t xi = x[i] & mask;
+    const uint64_t xi = x[i];
     const cplx<T> a = psi[xi];
     const double p = (double)a.re * (double)a.re + (double)a.im * (double)a.im;
     const double s = 1.0 / ((double)m * p);
@@ -565,7 +566,7 @@ static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *
     *loss = -sum_log / (double)k;
     hipLaunchKernelGGL(k_zero<T>, dim3(ggrid(N)), dim3(BLOCK), 0, s, mu, N);
     hipLaunchKernelGGL(k_lambda<T>, dim3((unsigned)((k + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, phi, mu,
-                       dx, k, N - 1);
+                       dx, k);
     SV_HIP(hipGetLastError());
     // backward sweeps
     for (const Op &op : plan.bops) {
@@ -614,6 +615,8 @@ extern "C" sv_status sv_backward(sv_state *st, const sv_circuit *c, const sv_opt
     if (k <= 0 || !samples || !loss || (c->nparams > 0 && !grad))
         return fail(SV_EINVAL, "need samples, a loss and a gradient buffer");
     if (checkpoint_c < 0) return fail(SV_EINVAL, "checkpoint interval must be >= 0");
+    for (int64_t i = 0; i < k; i++)
+        if (samples[i] >= (1ull << st->n)) return fail(SV_ERANGE, "sv_backward: a sample is not an n-bit string");
     const bool ready = opts && (opts->flags & SV_FLAG_STATE_READY);
     if (ready && checkpoint_c != 0)
         return fail(SV_EINVAL, "SV_FLAG_STATE_READY needs checkpoint_c = 0 (no forward pass to store them)");

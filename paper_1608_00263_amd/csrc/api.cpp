@@ -306,7 +306,9 @@ sv_status sv_free(sv_state *st) {
 sv_status sv_reset(sv_state *st) {
     SV_TRY(check_state(st));
     SV_TRY(launch_init_zero(st, st->data));
-    st->known_zero = true;
+    // only a buffer the library owns stays |0..0> until the next call: the
+    // caller may write an attached buffer at any time
+    st->known_zero = st->owned;
     return SV_OK;
 }
 
@@ -470,7 +472,7 @@ sv_status sv_moments_sample(sv_state *st, sv_stats *stats, int64_t k, uint64_t s
 sv_status sv_sample_from(const double *probs, uint64_t N, const uint64_t *r64, int64_t k, uint64_t *out,
                          void *hip_stream) {
     if (!probs || !r64 || (k > 0 && !out)) return fail(SV_EINVAL, "null pointer");
-    if (N < 1 || N > (1ull << 35)) return fail(SV_ERANGE, "N out of range");
+    if (N < 1 || N > (1ull << 35)) return fail(SV_ERANGE, "N out of range 1..2^35");
     if (k < 0 || k > ((int64_t)1 << 31)) return fail(SV_ERANGE, "sample count out of range");
     return run_sample_from(probs, N, r64, k, out, (hipStream_t)hip_stream);
 }
@@ -480,6 +482,8 @@ sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k, dou
     SV_TRY(check_state(st));
     if (k <= 0 || !samples || !ce) return fail(SV_EINVAL, "need k > 0 samples and an output");
     if (!(norm <= 0.0 || std::isfinite(norm))) return fail(SV_EINVAL, "norm must be finite");
+    for (int64_t i = 0; i < k; i++)
+        if (samples[i] >= (1ull << st->n)) return fail(SV_ERANGE, "sv_cross_entropy: a sample is not an n-bit string");
     double S = norm;
     if (!(norm > 0.0)) SV_TRY(run_norm(st, st->data, &S));
     SV_TRY(st->ws2.reserve((size_t)k * 8));

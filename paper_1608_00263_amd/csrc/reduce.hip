@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 
 #include "internal.h"
 #include "reduce_common.h"
@@ -240,8 +241,10 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
+// Entries at index >= N (the ragged end of an explicit distribution whose
+// length is not a power of two) have weight 0 and are not read.
 template <typename S>
-__global__ __launch_bounds__(RB) void k_bucket_weights(const S *__restrict__ src, int bs, int sb,
+__global__ __launch_bounds__(RB) void k_bucket_weights(const S *__restrict__ src, uint64_t N, int bs, int sb,
                                                        unsigned long long *__restrict__ bsum,
                                                        unsigned long long *__restrict__ subsum) {
     __shared__ unsigned long long sh[64];
@@ -251,7 +254,8 @@ __global__ __launch_bounds__(RB) void k_bucket_weights(const S *__restrict__ src
     for (int j = wave; j < nsub; j += RB / 64) {
         const uint64_t start = ((uint64_t)blockIdx.x << bs) + ((uint64_t)j << sb);
         unsigned long long acc = 0;
-        for (uint64_t e = lane; e < slen; e += 64) acc += weight_of(prob_of(src[start + e]));
+        for (uint64_t e = lane; e < slen; e += 64)
+            if (start + e < N) acc += weight_of(prob_of(src[start + e]));
         acc = wave_sum_u64(acc);
         if (lane == 0) {
             subsum[(uint64_t)blockIdx.x * nsub + j] = acc;
@@ -395,7 +399,7 @@ __device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long l
 // sub-bucket whose running sum exceeds it), then the lane run of R
 // consecutive entries holding it, then the entry: x = min{j : C_j > t}.
 template <typename S>
-__global__ __launch_bounds__(RB) void k_resolve(const S *__restrict__ src, int bs, int sb,
+__global__ __launch_bounds__(RB) void k_resolve(const S *__restrict__ src, uint64_t N, int bs, int sb,
                                                 const unsigned long long *__restrict__ subsum,
                                                 const uint32_t *__restrict__ tb,
                                                 const unsigned long long *__restrict__ tloc, int64_t k,
@@ -421,7 +425,10 @@ __global__ __launch_bounds__(RB) void k_resolve(const S *__restrict__ src, int b
     const bool has = lane * R < slen;
     unsigned long long run = 0;
     if (has)
-        for (int e = 0; e < R; e++) run += weight_of(prob_of(src[start + (uint64_t)lane * R + e]));
+        for (int e = 0; e < R; e++) {
+            const uint64_t x = start + (uint64_t)lane * R + e;
+            if (x < N) run += weight_of(prob_of(src[x]));
+        }
     const unsigned long long rincl = wave_incl_scan_u64(run, lane);
     const unsigned long long hit = __ballot(has && rincl > ts);
     int L = __ffsll((long long)hit) - 1;
@@ -430,7 +437,8 @@ __global__ __launch_bounds__(RB) void k_resolve(const S *__restrict__ src, int b
         unsigned long long c = rincl - run;
         uint64_t ans = start + (uint64_t)lane * R + (R - 1);
         for (int e = 0; e < R; e++) {
-            c += weight_of(prob_of(src[start + (uint64_t)lane * R + e]));
+            const uint64_t x = start + (uint64_t)lane * R + e;
+            if (x < N) c += weight_of(prob_of(src[x]));
             if (c > ts) {
                 ans = start + (uint64_t)lane * R + e;
                 break;
@@ -440,26 +448,77 @@ __global__ __launch_bounds__(RB) void k_resolve(const S *__restrict__ src, int b
     }
 }
 
+// Device scratch of the sampler: a workspace grown on demand, or a fixed
+// buffer of cap bytes that must already be large enough.
+struct ScratchSource {
+    Workspace *ws = nullptr;
+    void *fixed = nullptr;
+    size_t cap = 0;
+};
+
+static sv_status take_scratch(const ScratchSource &scr, size_t need, uint8_t **out) {
+    if (scr.ws) {
+        SV_TRY(scr.ws->reserve(need));
+        *out = (uint8_t *)scr.ws->ptr;
+        return SV_OK;
+    }
+    if (need > scr.cap) {
+        char b[160];
+        snprintf(b, sizeof b, "needs %zu bytes of scratch, the fixed scratch holds %zu", need, scr.cap);
+        return fail(SV_ERANGE, b);
+    }
+    *out = (uint8_t *)scr.fixed;
+    return SV_OK;
+}
+
+// Layout of the sampler's scratch for 2^n entries and k samples (with the
+// statistics rows when stats is set): byte offsets of its parts and the
+// total.
+struct SampleLayout {
+    int bs, sb;
+    uint64_t nb, nsubs, ng;
+    size_t o_bsum, o_off, o_sub, o_tb, o_tl, o_part, o_res, need;
+};
+
+static SampleLayout sample_layout(int n, int64_t k, bool stats) {
+    SampleLayout L{};
+    L.bs = n < 16 ? n : 16;
+    L.sb = L.bs < SUB_BITS ? L.bs : SUB_BITS;
+    L.nb = 1ull << (n - L.bs);
+    L.nsubs = 1ull << (n - L.sb);
+    L.ng = L.nb < 2048 ? L.nb : 2048;   // workgroups of the fused statistics pass
+    size_t need = 0;
+    auto take = [&](size_t bytes) { size_t o = need; need += (bytes + 255) & ~(size_t)255; return o; };
+    L.o_bsum = take(L.nb * 8);
+    L.o_off = take((L.nb + 1) * 8);
+    L.o_sub = take(L.nsubs * 8);
+    L.o_tb = take((size_t)k * 4);
+    L.o_tl = take((size_t)k * 8);
+    L.o_part = stats ? take(L.ng * 16 * 8) : 0;
+    L.o_res = stats ? take(16 * 8) : 0;
+    L.need = need;
+    return L;
+}
+
 // The sampler; with stats16 non-null (states only) the bucket weights come
 // from the fused statistics pass, whose 14 combined sums are copied to
 // stats16 (and k may be 0).
+// src holds N = 2^n entries, or (explicit distributions) any N in
+// (2^{n-1}, 2^n], the entries beyond N counting as weight 0.
 template <typename S>
-static sv_status sample_impl(Workspace *ws, hipStream_t s, const S *src, int n, const uint64_t *words,
-                             uint64_t seed, int64_t k, uint64_t *dev_out, double *stats16 = nullptr) {
+static sv_status sample_impl(const ScratchSource &scr, hipStream_t s, const S *src, int n, const uint64_t *words,
+                             uint64_t seed, int64_t k, uint64_t *dev_out, double *stats16 = nullptr,
+                             uint64_t N = 0) {
+    if (N == 0) N = 1ull << n;
     if (k <= 0 && !stats16) return SV_OK;
     if (k < 0) k = 0;
-    const int bs = n < 16 ? n : 16;
-    const int sb = bs < SUB_BITS ? bs : SUB_BITS;
-    const uint64_t nb = 1ull << (n - bs);
-    const uint64_t nsubs = 1ull << (n - sb);
-    size_t need = 0;
-    auto take = [&](size_t bytes) { size_t o = need; need += (bytes + 255) & ~(size_t)255; return o; };
-    size_t o_bsum = take(nb * 8), o_off = take((nb + 1) * 8), o_sub = take(nsubs * 8),
-           o_tb = take((size_t)k * 4), o_tl = take((size_t)k * 8);
-    const uint64_t ng = nb < 2048 ? nb : 2048;   // workgroups of the fused statistics pass
-    const size_t o_part = stats16 ? take(ng * 16 * 8) : 0, o_res = stats16 ? take(16 * 8) : 0;
-    SV_TRY(ws->reserve(need));
-    uint8_t *w = (uint8_t *)ws->ptr;
+    const SampleLayout L = sample_layout(n, k, stats16 != nullptr);
+    const int bs = L.bs, sb = L.sb;
+    const uint64_t nb = L.nb, ng = L.ng;
+    const size_t o_bsum = L.o_bsum, o_off = L.o_off, o_sub = L.o_sub, o_tb = L.o_tb, o_tl = L.o_tl,
+                 o_part = L.o_part, o_res = L.o_res;
+    uint8_t *w = nullptr;
+    SV_TRY(take_scratch(scr, L.need, &w));
     auto *bsum = (unsigned long long *)(w + o_bsum);
     auto *off = (unsigned long long *)(w + o_off);
     auto *sub = (unsigned long long *)(w + o_sub);
@@ -477,7 +536,7 @@ static sv_status sample_impl(Workspace *ws, hipStream_t s, const S *src, int n, 
             return SV_OK;
         }
     } else {
-        hipLaunchKernelGGL((k_bucket_weights<S>), dim3((unsigned)nb), dim3(RB), 0, s, src, bs, sb, bsum, sub);
+        hipLaunchKernelGGL((k_bucket_weights<S>), dim3((unsigned)nb), dim3(RB), 0, s, src, N, bs, sb, bsum, sub);
     }
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, bsum, nb, off);
     unsigned long long W = 0;
@@ -487,41 +546,119 @@ static sv_status sample_impl(Workspace *ws, hipStream_t s, const S *src, int n, 
     const unsigned kg = (unsigned)((k + RB - 1) / RB);
     hipLaunchKernelGGL(k_targets, dim3(kg), dim3(RB), 0, s, words, seed, k, off, nb, tb, tl);
     const unsigned rg = (unsigned)((k + RB / 64 - 1) / (RB / 64));
-    hipLaunchKernelGGL((k_resolve<S>), dim3(rg), dim3(RB), 0, s, src, bs, sb, sub, tb, tl, k, dev_out);
+    hipLaunchKernelGGL((k_resolve<S>), dim3(rg), dim3(RB), 0, s, src, N, bs, sb, sub, tb, tl, k, dev_out);
     SV_HIP(hipGetLastError());
     return SV_OK;
 }
 
 sv_status run_sample(sv_state *st, const void *psi, int64_t k, uint64_t seed, uint64_t *dev_out) {
+    ScratchSource scr;
+    scr.ws = &st->ws;
     if (st->dt == SV_C64)
-        return sample_impl<cpx<float>>(&st->ws, st->stream, (const cpx<float> *)psi, st->n, nullptr,
+        return sample_impl<cpx<float>>(scr, st->stream, (const cpx<float> *)psi, st->n, nullptr,
                                        seed, k, dev_out);
-    return sample_impl<cpx<double>>(&st->ws, st->stream, (const cpx<double> *)psi, st->n, nullptr,
+    return sample_impl<cpx<double>>(scr, st->stream, (const cpx<double> *)psi, st->n, nullptr,
                                     seed, k, dev_out);
+}
+
+static sv_status stats_sample_from(const ScratchSource &scr, sv_state *st, const void *psi, sv_stats *stats,
+                                   int64_t k, uint64_t seed, uint64_t *dev_out) {
+    double r[16] = {0};
+    if (st->dt == SV_C64)
+        SV_TRY(sample_impl<cpx<float>>(scr, st->stream, (const cpx<float> *)psi, st->n, nullptr, seed, k,
+                                       dev_out, r));
+    else
+        SV_TRY(sample_impl<cpx<double>>(scr, st->stream, (const cpx<double> *)psi, st->n, nullptr, seed, k,
+                                        dev_out, r));
+    finish_stats(st->n, r, stats);
+    return SV_OK;
 }
 
 sv_status run_stats_sample(sv_state *st, const void *psi, sv_stats *stats, int64_t k, uint64_t seed,
                            uint64_t *dev_out) {
-    double r[16] = {0};
-    if (st->dt == SV_C64)
-        SV_TRY(sample_impl<cpx<float>>(&st->ws, st->stream, (const cpx<float> *)psi, st->n, nullptr, seed, k,
-                                       dev_out, r));
-    else
-        SV_TRY(sample_impl<cpx<double>>(&st->ws, st->stream, (const cpx<double> *)psi, st->n, nullptr, seed, k,
-                                        dev_out, r));
-    finish_stats(st->n, r, stats);
-    return SV_OK;
+    ScratchSource scr;
+    scr.ws = &st->ws;
+    return stats_sample_from(scr, st, psi, stats, k, seed, dev_out);
+}
+
+// Validation of an explicit distribution for the integer-CDF sampler: every
+// p must be finite, >= 0 and < 4 (its weight floor(p 2^62) fits 64 bits),
+// and the weights must sum below 2^64.  Per workgroup, the exact 128-bit
+// sum of the weights of its 2^16 entries (high and low words) and a flag for
+// an invalid entry; one more workgroup adds the rows (high words cannot
+// overflow: at most 2^19 rows of at most 2^80 each).
+constexpr int VAL_BITS = 16;
+
+__global__ __launch_bounds__(RB) void k_validate_weights(const double *__restrict__ p, uint64_t N,
+                                                         unsigned long long *__restrict__ rows) {
+    __shared__ unsigned long long slo[RB], shi[RB];
+    __shared__ unsigned sbad[RB];
+    const uint64_t start = (uint64_t)blockIdx.x << VAL_BITS;
+    unsigned long long lo = 0, hi = 0;
+    unsigned bad = 0;
+    for (uint64_t e = threadIdx.x; e < (1ull << VAL_BITS); e += RB) {
+        const uint64_t x = start + e;
+        if (x >= N) break;
+        const double v = p[x];
+        if (!(v >= 0.0) || !(v < 4.0)) { bad = 1; continue; }   // NaN, negative, >= 4, inf
+        const unsigned long long w = weight_of(v);
+        lo += w;
+        hi += lo < w ? 1ull : 0ull;
+    }
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    sbad[threadIdx.x] = bad;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long L = 0, H = 0;
+        unsigned B = 0;
+        for (int t = 0; t < RB; t++) {
+            L += slo[t];
+            H += shi[t] + (L < slo[t] ? 1ull : 0ull);
+            B |= sbad[t];
+        }
+        rows[3 * (uint64_t)blockIdx.x] = L;
+        rows[3 * (uint64_t)blockIdx.x + 1] = H;
+        rows[3 * (uint64_t)blockIdx.x + 2] = B;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_validate_total(const unsigned long long *__restrict__ rows, uint64_t nrows,
+                                                       unsigned long long *__restrict__ out) {
+    if (threadIdx.x != 0) return;
+    unsigned long long L = 0, H = 0, B = 0;
+    for (uint64_t r = 0; r < nrows; r++) {
+        const unsigned long long l = rows[3 * r];
+        L += l;
+        H += rows[3 * r + 1] + (L < l ? 1ull : 0ull);
+        B |= rows[3 * r + 2];
+    }
+    out[0] = L;
+    out[1] = H;
+    out[2] = B;
 }
 
 sv_status run_sample_from(const double *probs, uint64_t N, const uint64_t *r64, int64_t k,
                           uint64_t *out, hipStream_t s) {
     int n = 0;
     while ((1ull << n) < N) n++;
-    if ((1ull << n) != N) return fail(SV_EINVAL, "sv_sample_from: N must be a power of two");
     // library-owned scratch for this standalone call; kept until the process
     // ends (never freed from a static destructor, after the runtime is gone)
-    static Workspace *ws = new Workspace();
-    sv_status rc = sample_impl<double>(ws, s, probs, n, r64, 0, k, out);
+    static ScratchSource *scr = new ScratchSource{new Workspace(), nullptr, 0};
+    static Workspace *vws = new Workspace();
+    const uint64_t nrows = (N + (1ull << VAL_BITS) - 1) >> VAL_BITS;
+    SV_TRY(vws->reserve((size_t)(nrows + 1) * 3 * 8));
+    auto *rows = (unsigned long long *)vws->ptr;
+    hipLaunchKernelGGL(k_validate_weights, dim3((unsigned)nrows), dim3(RB), 0, s, probs, N, rows);
+    hipLaunchKernelGGL(k_validate_total, dim3(1), dim3(64), 0, s, rows, nrows, rows + 3 * nrows);
+    SV_HIP(hipGetLastError());
+    unsigned long long tot[3] = {0, 0, 0};
+    SV_HIP(hipMemcpyAsync(tot, rows + 3 * nrows, sizeof tot, hipMemcpyDeviceToHost, s));
+    SV_HIP(hipStreamSynchronize(s));
+    if (tot[2]) return fail(SV_EINVAL, "sv_sample_from: a probability is negative, NaN, infinite or >= 4");
+    if (tot[1]) return fail(SV_ERANGE, "sv_sample_from: the weights floor(p 2^62) sum to 2^64 or more (sum p >= 4)");
+    if (k == 0) return SV_OK;
+    sv_status rc = sample_impl<double>(*scr, s, probs, n, r64, 0, k, out, nullptr, N);
     if (rc != SV_OK) return rc;
     SV_HIP(hipStreamSynchronize(s));
     return SV_OK;
@@ -530,8 +667,9 @@ sv_status run_sample_from(const double *probs, uint64_t N, const uint64_t *r64, 
 // ---------------------------------------------------------------------------
 // sample cross entropy: sum_i ln p(x_i) and the number of p(x_i) = 0
 // ---------------------------------------------------------------------------
+// Samples are n-bit strings (checked on the host before the copy).
 template <typename T>
-__global__ __launch_bounds__(RB) void k_ce(const cpx<T> *__restrict__ psi, uint64_t mask,
+__global__ __launch_bounds__(RB) void k_ce(const cpx<T> *__restrict__ psi,
                                            const uint64_t *__restrict__ x, int64_t k, int64_t per,
                                            double *__restrict__ part) {
     __shared__ double red[4 * 2];
@@ -539,7 +677,7 @@ __global__ __launch_bounds__(RB) void k_ce(const cpx<T> *__restrict__ psi, uint6
     const int64_t b = (int64_t)blockIdx.x * per;
     const int64_t e = b + per < k ? b + per : k;
     for (int64_t i = b + threadIdx.x; i < e; i += RB) {
-        const double p = prob_of(psi[x[i] & mask]);
+        const double p = prob_of(psi[x[i]]);
         if (p > 0.0) v[0] += log(p);
         else v[1] += 1.0;
     }
@@ -556,13 +694,12 @@ sv_status run_cross_entropy(sv_state *st, const void *psi, const uint64_t *dev_s
     SV_TRY(st->ws.reserve((size_t)(nb + 1) * 16 * sizeof(double)));
     double *part = (double *)st->ws.ptr;
     double *res = part + (size_t)nb * 16;
-    const uint64_t mask = (1ull << st->n) - 1;
     if (st->dt == SV_C64)
         hipLaunchKernelGGL(k_ce<float>, dim3((unsigned)nb), dim3(RB), 0, st->stream,
-                           (const cpx<float> *)psi, mask, dev_samples, k, per, part);
+                           (const cpx<float> *)psi, dev_samples, k, per, part);
     else
         hipLaunchKernelGGL(k_ce<double>, dim3((unsigned)nb), dim3(RB), 0, st->stream,
-                           (const cpx<double> *)psi, mask, dev_samples, k, per, part);
+                           (const cpx<double> *)psi, dev_samples, k, per, part);
     SV_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, st->stream, part, (int)nb, 2, res);
     double r[2];

@@ -431,3 +431,131 @@ def test_ensemble_recipe_small():
         want = oracle.stats(oracle.probs(ref))
         assert abs(r["entropy"] - want["entropy"]) < 1e-4
         st.close()
+
+
+# ---------------------------------------------------------------------------
+# statuses of the sample-based calls (samples are n-bit strings, Sec. II)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_cross_entropy_zero_probability_and_range(dtype):
+    n = 12
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    psi = C.random_state(n, 80, dtype=npdt)
+    zero_at = np.array([5, 77, 2049])
+    psi[zero_at] = 0
+    st = sv.State(n, dtype, tensor=torch.from_numpy(psi).to("cuda"))
+    p = oracle.probs(psi)
+    xs = np.concatenate([oracle.sample(p, 500, 9), zero_at[:2], zero_at[:1]]).astype(np.uint64)
+    ce, dh, z = st.cross_entropy(xs)
+    ce0, dh0, z0 = oracle.cross_entropy(p, xs)
+    assert math.isinf(ce) and math.isinf(ce0) and z == z0 == 3
+    bad = xs.copy()
+    bad[10] = np.uint64(1 << n)
+    with pytest.raises(sv.SVError) as e:
+        st.cross_entropy(bad)
+    assert e.value.status == sv.SV_ERANGE
+    with pytest.raises(ValueError):
+        oracle.cross_entropy(p, bad)
+    st.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_backward_zero_probability_and_range(dtype):
+    # Hadamard layer, then H on qubit 0 again: qubit 0 is back in |0>, so every
+    # x with bit 0 set has p = 0 in exact arithmetic.  In floating point the
+    # zero is exact only where the two amplitudes the second H combines are
+    # still equal powers of two: a phase on a bit of x, or a dense gate the
+    # planner may move ahead of that H, leaves a rounding residue (about 1e-19
+    # in complex64).  Here the rotations act on qubits 2 and 3, so x = 1
+    # (bits 2, 3 clear) is an exact zero whatever order the commuting gates
+    # take; x = 3 is not a sample.
+    n = 8
+    recs = [(C.H, q, -1, 0, -1, -1) for q in range(n)]
+    recs += [(C.H, 0, -1, 1, -1, -1), (C.T, 3, -1, 1, 0, -1), (C.T, 2, -1, 2, 1, -1)]
+    circ = C.Circuit(n=n, gates=C.make_gates(recs), theta=np.array([0.1, -0.2]), depth=2)
+    ok = np.array([0, 2, 6, 254, 12], dtype=np.uint64)
+    loss0, g0 = oracle.adjoint(circ, ok)
+    st = sv.State(n, dtype)
+    loss, g = st.backward(circ, ok)
+    tol = 1e-9 if dtype == "c128" else 1e-5
+    assert abs(loss - loss0) < tol and np.abs(g - g0).max() < tol
+    with_zero = np.array([0, 1, 6], dtype=np.uint64)
+    with pytest.raises(ValueError):
+        oracle.adjoint(circ, with_zero)
+    with pytest.raises(sv.SVError) as e:
+        st.backward(circ, with_zero)
+    assert e.value.status == sv.SV_ESTATE
+    with pytest.raises(sv.SVError) as e:
+        st.backward(circ, np.array([0, 1 << n], dtype=np.uint64))
+    assert e.value.status == sv.SV_ERANGE
+    st.close()
+
+
+@pytest.mark.parametrize("N,zeros,k", [(1, 0, 40), (3, 1, 500), (1000, 17, 4000), (70001, 300, 20000),
+                                        ((1 << 17) + 5, 0, 10000)])
+def test_sample_from_any_length_bit_exact(N, zeros, k):
+    # lengths that are not powers of two: the entries beyond N never exist
+    p = C.random_probabilities(N, 90 + N % 97, zeros=zeros)
+    words = C.splitmix64_words(91, k)
+    want = oracle.sample_from_words(p, words)
+    got = sv.sample_from(torch.from_numpy(p).to("cuda"),
+                         torch.from_numpy(words.view(np.int64)).to("cuda")).cpu().numpy()
+    np.testing.assert_array_equal(got.view(np.uint64), want)
+    assert (want < N).all()
+
+
+def test_sample_from_statuses():
+    words = torch.from_numpy(C.splitmix64_words(5, 64).view(np.int64)).to("cuda")
+
+    def run(vals):
+        return sv.sample_from(torch.tensor(vals, dtype=torch.float64, device="cuda"), words)
+
+    x = run([1.99, 1.99]).cpu().numpy()
+    np.testing.assert_array_equal(x.view(np.uint64),
+                                  oracle.sample_from_words(np.array([1.99, 1.99]), C.splitmix64_words(5, 64)))
+    for vals, status in (([2.0, 2.0], sv.SV_ERANGE), ([3.0, 0.5, 0.75], sv.SV_ERANGE),
+                         ([4.0, 0.0], sv.SV_EINVAL), ([-0.5, 1.0], sv.SV_EINVAL),
+                         ([float("nan"), 1.0], sv.SV_EINVAL), ([float("inf")], sv.SV_EINVAL),
+                         ([0.0, 0.0, 0.0], sv.SV_ESTATE)):
+        with pytest.raises(sv.SVError) as e:
+            run(vals)
+        assert e.value.status == status, vals
+        with pytest.raises(ValueError):
+            oracle.sample_from_words(np.array(vals), C.splitmix64_words(5, 64))
+
+
+def test_attached_buffer_written_after_reset():
+    # reset() of a caller-owned buffer, then the caller writes it: the next
+    # circuit must act on what the caller wrote, not on |0..0>
+    circ = C.make_circuit(3, 4, 12, seed=95)
+    psi0 = C.random_state(circ.n, 96, dtype=np.complex128)
+    ref = oracle.apply_circuit(circ, psi0.copy())
+    for dtype, tol in (("c64", 1e-4), ("c128", 1e-11)):
+        st = sv.State(circ.n, dtype)
+        st.reset()
+        st.tensor.copy_(torch.from_numpy(psi0).to(st.tensor.dtype))
+        st.apply(circ, "auto")
+        assert np.linalg.norm(st.amplitudes() - ref) <= tol
+        st.close()
+
+
+def test_autograd_two_forwards_then_one_backward():
+    from paper_1608_00263_amd.autograd import CircuitCrossEntropy
+    circ = C.make_circuit(3, 4, 14, seed=97, parametrise=True, theta_seed=98, theta_std=0.05)
+    p0 = oracle.probs(oracle.apply_circuit(circ.with_theta(np.zeros(circ.nparams))))
+    xs = oracle.sample(p0, 2000, 1009)
+    f = CircuitCrossEntropy(circ, xs, dtype="c128")
+    t1 = torch.tensor(circ.theta, dtype=torch.float64, requires_grad=True)
+    t2 = torch.tensor(circ.theta * -0.7, dtype=torch.float64, requires_grad=True)
+    l1 = f(t1)
+    l2 = f(t2)                       # the state now holds the second forward's output
+    (l1 + 2.0 * l2).backward(retain_graph=True)
+    _, g1 = oracle.adjoint(circ.with_theta(circ.theta), xs)
+    _, g2 = oracle.adjoint(circ.with_theta(circ.theta * -0.7), xs)
+    np.testing.assert_allclose(t1.grad.numpy(), g1, atol=1e-9)
+    np.testing.assert_allclose(t2.grad.numpy(), 2.0 * g2, atol=1e-9)
+    # a second backward through the same graph (the state was uncomputed by
+    # the first): gradients accumulate
+    l1.backward()
+    np.testing.assert_allclose(t1.grad.numpy(), 2.0 * g1, atol=1e-9)
+    f.close()
