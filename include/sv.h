@@ -234,6 +234,22 @@ sv_status sv_sample(sv_state *st, int64_t k, uint64_t seed, uint64_t *out, int o
 sv_status sv_moments_sample(sv_state *st, sv_stats *stats, int64_t k, uint64_t seed, uint64_t *out,
                             int out_on_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * statistics and samples of sv_moments_sample, computed by the same kernels
+ * (bit-identical results), with every intermediate in one fixed 64 MiB
+ * device array that comes with the library's code object on each GPU and is
+ * held until the process ends; the call allocates nothing.  dev_out is
+ * device memory (k entries, caller-owned; may be NULL when k = 0); stats is
+ * a host struct.  The scratch must hold 8 2^(n-10) + 16 2^(n-16) + 12 k
+ * bytes plus about 33 KiB of rows (n <= 32; e.g. k up to 4.8 million at
+ * n = 30): SV_ERANGE otherwise, before any device work.  Every call on one
+ * GPU shares that array and leaves its contents behind (nothing in it needs
+ * to start at zero), so calls that overlap on one GPU race: serialise them
+ * (one stream, or a host lock).  Synchronises the handle's stream. */
+sv_status sv_moments_sample_noalloc(sv_state *st, sv_stats *stats, int64_t k, uint64_t seed,
+                                    uint64_t *dev_out);
+
 /* The same sampler on an explicit distribution: probs (device, N doubles,
  * need not sum to 1), r64 (device, k random words used as the r_i above),
  * out (device, k entries, caller-owned).  N is any length in 1..2^35 (else

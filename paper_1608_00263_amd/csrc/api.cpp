@@ -469,6 +469,16 @@ sv_status sv_moments_sample(sv_state *st, sv_stats *stats, int64_t k, uint64_t s
     return SV_OK;
 }
 
+sv_status sv_moments_sample_noalloc(sv_state *st, sv_stats *stats, int64_t k, uint64_t seed, uint64_t *dev_out) {
+    SV_TRY(check_state(st));
+    if (!stats) return fail(SV_EINVAL, "null statistics output");
+    if (k < 0 || k > ((int64_t)1 << 31)) return fail(SV_ERANGE, "sample count out of range");
+    if (k > 0 && !dev_out) return fail(SV_EINVAL, "null device output");
+    SV_TRY(run_stats_sample_noalloc(st, stats, k, seed, dev_out));
+    SV_HIP(hipStreamSynchronize(st->stream));
+    return SV_OK;
+}
+
 sv_status sv_sample_from(const double *probs, uint64_t N, const uint64_t *r64, int64_t k, uint64_t *out,
                          void *hip_stream) {
     if (!probs || !r64 || (k > 0 && !out)) return fail(SV_EINVAL, "null pointer");

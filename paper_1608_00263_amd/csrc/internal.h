@@ -330,6 +330,11 @@ sv_status run_stats_sample(sv_state *st, const void *psi, sv_stats *stats, int64
                            uint64_t *dev_out);
 sv_status run_sample_from(const double *probs, uint64_t N, const uint64_t *r64,
                           int64_t k, uint64_t *out, hipStream_t s);
+// sv_moments_sample on the fixed device scratch (no allocation); the bytes
+// of scratch it needs for (n, k), and the fixed scratch size
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+size_t noalloc_scratch_need(int n, int64_t k);
+sv_status run_stats_sample_noalloc(sv_state *st, sv_stats *stats, int64_t k, uint64_t seed, uint64_t *dev_out);
 sv_status run_cross_entropy(sv_state *st, const void *psi, const uint64_t *dev_samples,
                             int64_t k, double S, double *sum_log, int64_t *zeros);
 

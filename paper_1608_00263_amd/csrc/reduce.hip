@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 
 #include "internal.h"
 #include "reduce_common.h"
@@ -579,6 +580,53 @@ sv_status run_stats_sample(sv_state *st, const void *psi, sv_stats *stats, int64
     ScratchSource scr;
     scr.ws = &st->ws;
     return stats_sample_from(scr, st, psi, stats, k, seed, dev_out);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free statistics and samples
+// ---------------------------------------------------------------------------
+// The scratch of sv_moments_sample_noalloc: device memory that comes with
+// the code object on every GPU the library runs on (held until the process
+// ends), so the call needs no allocation.  Host code never uses this name
+// as an address: its device address on each GPU is looked up once, with
+// that GPU current, and kept per device.
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES] = {};
+
+static sv_status noalloc_scratch(int device, void **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= MAX_DEVICES) return fail(SV_EDEVICE, "device index out of range");
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        SV_HIP(hipGetDevice(&cur));
+        if (cur != device) SV_HIP(hipSetDevice(device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return SV_OK;
+}
+
+size_t noalloc_scratch_need(int n, int64_t k) { return sample_layout(n, k, true).need; }
+
+sv_status run_stats_sample_noalloc(sv_state *st, sv_stats *stats, int64_t k, uint64_t seed, uint64_t *dev_out) {
+    const size_t need = noalloc_scratch_need(st->n, k);
+    if (need > NOALLOC_SCRATCH_BYTES) {
+        char b[200];
+        snprintf(b, sizeof b, "sv_moments_sample_noalloc: n = %d and k = %lld need %zu bytes of scratch, "
+                 "the fixed scratch holds %zu", st->n, (long long)k, need, (size_t)NOALLOC_SCRATCH_BYTES);
+        return fail(SV_ERANGE, b);
+    }
+    ScratchSource scr;
+    SV_TRY(noalloc_scratch(st->device, &scr.fixed));
+    scr.cap = NOALLOC_SCRATCH_BYTES;
+    return stats_sample_from(scr, st, st->data, stats, k, seed, dev_out);
 }
 
 // Validation of an explicit distribution for the integer-CDF sampler: every
