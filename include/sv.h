@@ -216,6 +216,23 @@ sv_status sv_probs(sv_state *st, uint64_t begin, uint64_t count, int out_f64, vo
  * deterministic).  Synchronises. */
 sv_status sv_moments(sv_state *st, sv_stats *out);
 
+/* Statistics after every cycle (Sec. IV: the entropy, the uniform cross
+ * entropy and the moments of the output distribution measured after each
+ * cycle t, as in its figures of the approach to Porter-Thomas): simulate c
+ * from |0...0> and write to out[t] (host, t = 0..D, D = the largest gate
+ * cycle; the cycle of a gate is sv_gate.cycle, 0 = the Hadamard layer) the
+ * statistics of the state after the gates of cycles 0..t.  Gates must be
+ * listed in nondecreasing cycle order (SV_EINVAL otherwise).  A cycle whose
+ * gates are all diagonal (CZ, T, phases) leaves every probability unchanged
+ * and reports the previous cycle's statistics without a pass over the state;
+ * diagonal gates may be applied across a cycle's end for the same reason,
+ * dense gates never are.  opts: SV_MODE_REGTILE (AUTO: register tiles of
+ * the default width), SV_MODE_SPEC or SV_MODE_PLAIN, else SV_EINVAL.
+ * *ncycles (may be NULL) gets D + 1; SV_ERANGE if cap < D + 1.  On return
+ * the state holds the circuit's output U|0...0>.  Synchronises. */
+sv_status sv_cycle_moments(sv_state *st, const sv_circuit *c, const sv_opts *opts, int64_t cap,
+                           sv_stats *out, int64_t *ncycles);
+
 /* Draw k bit-strings from p(x) = |<x|psi>|^2 (Sec. II, the sample S).
  * Exactly reproducible inverse-transform sampling on an integer CDF:
  * w_x = floor(p(x) 2^62), C_x = w_0 + ... + w_x, W = C_{2^n - 1};

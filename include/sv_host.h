@@ -32,6 +32,16 @@ sv_status sv_host_plan(const sv_circuit *c, sv_dtype dt, const sv_opts *opts, in
 sv_status sv_host_emulate(const sv_circuit *c, sv_dtype dt, const sv_opts *opts, int from_zero,
                           double *psi);
 
+/* Replay of the plan sv_cycle_moments runs for (c, dt, opts) from |0...0>
+ * (n <= 26): probs (host, cap_rows x 2^n doubles, may be NULL) gets
+ * |psi_x|^2 at each statistics point of the plan, row by row; cycle_row
+ * (host, cap_cycles entries, may be NULL) the row that reports each cycle
+ * t = 0..D; *nrows and *ncycles (may be NULL) their numbers.  SV_ERANGE if
+ * cap_rows or cap_cycles is too small (the counts are still written). */
+sv_status sv_host_cycle_emulate(const sv_circuit *c, sv_dtype dt, const sv_opts *opts, int64_t cap_rows,
+                                double *probs, int32_t *cycle_row, int64_t cap_cycles, int64_t *nrows,
+                                int64_t *ncycles);
+
 /* Text description of that plan, one line per sweep (kind, tile qubits,
  * gate and term counts), written to buf (NUL-terminated, at most cap
  * bytes, truncated if longer). */

@@ -110,6 +110,26 @@ def stats(p: np.ndarray) -> dict:
     return d
 
 
+def cycle_stats(circ) -> list:
+    """Statistics after every cycle (Sec. IV: the output distribution is
+    measured after each cycle t): for t = 0..D, the gates of cycles 0..t
+    applied to |0..0> in list order, then stats() of the probabilities.
+    Gates must be listed in nondecreasing cycle order."""
+    cyc = np.asarray(circ.gates["cycle"])
+    if cyc.size and (np.diff(cyc) < 0).any():
+        raise ValueError("gate cycles must be nondecreasing")
+    D = int(cyc.max()) if cyc.size else 0
+    psi = zero_state(circ.n)
+    out = []
+    first = 0
+    for t in range(D + 1):
+        last = first + int((cyc == t).sum())
+        apply_circuit(circ, psi, first, last)
+        out.append(stats(probs(psi)))
+        first = last
+    return out
+
+
 def splitmix64(seed: int, i: int) -> int:
     return int(lib().orc_splitmix64(seed, i))
 

@@ -420,6 +420,49 @@ sv_status sv_plan_info(sv_state *st, const sv_circuit *c, const sv_opts *opts, i
     return SV_OK;
 }
 
+sv_status sv_cycle_moments(sv_state *st, const sv_circuit *c, const sv_opts *opts, int64_t cap, sv_stats *out,
+                           int64_t *ncycles) {
+    SV_TRY(check_state(st));
+    SV_TRY(check_circuit(st, c));
+    if (cap > 0 && !out) return fail(SV_EINVAL, "null statistics output");
+    PlanRequest rq = make_request(st, opts);
+    rq.from_zero = true;
+    rq.force_zero = true;
+    if (rq.budget != 0 && (rq.budget < 20 || rq.budget > 2000)) return fail(SV_EINVAL, "sweep_budget must be 0 or 20..2000");
+    const std::string key = "cyc:" + plan_key(c, rq);
+    std::shared_ptr<Plan> plan;
+    auto it = st->plans.find(key);
+    if (it != st->plans.end()) {
+        plan = it->second;
+    } else {
+        plan = std::make_shared<Plan>();
+        SV_TRY(build_cycle_plan(c, rq, plan.get()));
+        SV_TRY(upload_plan(st, plan.get()));
+        if (st->plans.size() > 64) st->plans.clear();
+        st->plans[key] = plan;
+    }
+    const int64_t nc = (int64_t)plan->cycle_row.size();
+    if (ncycles) *ncycles = nc;
+    if (cap < nc) return fail(SV_ERANGE, "per-cycle statistics: cap is smaller than the number of cycles");
+    int64_t nrows = 0;
+    for (const Op &op : plan->ops) nrows += op.type == OP_STATS;
+    SV_TRY(st->ws.reserve((size_t)(2048 + nrows) * 16 * sizeof(double)));
+    double *part = (double *)st->ws.ptr;
+    double *res = part + (size_t)2048 * 16;
+    for (const Op &op : plan->ops) {
+        if (op.type == OP_STATS) SV_TRY(batch_stats_enqueue(st, part, res + (size_t)16 * op.q0));
+        else SV_TRY(launch_op(st, *plan, op, st->data));
+    }
+    st->known_zero = false;
+    std::vector<double> host((size_t)nrows * 16);
+    SV_HIP(hipMemcpyAsync(host.data(), res, host.size() * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+    SV_HIP(hipStreamSynchronize(st->stream));
+    std::vector<sv_stats> rows((size_t)nrows);
+    for (int64_t r = 0; r < nrows; r++) finish_stats_row(st->n, &host[(size_t)16 * r], &rows[(size_t)r]);
+    for (int64_t t = 0; t < nc; t++) out[t] = rows[(size_t)plan->cycle_row[(size_t)t]];
+    return SV_OK;
+}
+
 sv_status sv_probs(sv_state *st, uint64_t begin, uint64_t count, int out_f64, void *dev_out) {
     SV_TRY(check_state(st));
     const uint64_t N = 1ull << st->n;

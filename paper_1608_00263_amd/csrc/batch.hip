@@ -40,7 +40,6 @@
 
 namespace svi {
 
-sv_status batch_stats_enqueue(sv_state *st, double *part, double *res);   // reduce.hip
 
 constexpr int TPI = 16;                 // register tiles per work item
 constexpr int STAT_BITS = 14;           // amplitudes per statistics item: 2^14

@@ -282,6 +282,43 @@ extern "C" sv_status sv_host_emulate(const sv_circuit *c, sv_dtype dt, const sv_
     return SV_OK;
 }
 
+extern "C" sv_status sv_host_cycle_emulate(const sv_circuit *c, sv_dtype dt, const sv_opts *opts, int64_t cap_rows,
+                                           double *probs, int32_t *cycle_row, int64_t cap_cycles, int64_t *nrows,
+                                           int64_t *ncycles) {
+    if (!c || c->n < 1 || c->n > 26) return fail(SV_ERANGE, "host replay limited to 1..26 qubits");
+    if (c->ngates < 0 || (c->ngates > 0 && !c->gates)) return fail(SV_EINVAL, "bad gate array");
+    PlanRequest rq{};
+    rq.n = c->n;
+    rq.dtype = dt;
+    rq.mode = opts ? opts->mode : SV_MODE_AUTO;
+    rq.tile = opts ? opts->tile_qubits : 0;
+    rq.budget = opts ? opts->sweep_budget : 0;
+    if (rq.budget != 0 && (rq.budget < 20 || rq.budget > 2000)) return fail(SV_EINVAL, "sweep_budget must be 0 or 20..2000");
+    rq.from_zero = true;
+    rq.force_zero = true;
+    Plan plan;
+    SV_TRY(build_cycle_plan(c, rq, &plan));
+    int64_t rows = 0;
+    for (const Op &op : plan.ops) rows += op.type == OP_STATS;
+    if (nrows) *nrows = rows;
+    if (ncycles) *ncycles = (int64_t)plan.cycle_row.size();
+    if (cap_rows < rows || cap_cycles < (int64_t)plan.cycle_row.size())
+        return fail(SV_ERANGE, "output arrays too small for the plan's rows and cycles");
+    const uint64_t N = 1ull << c->n;
+    std::vector<cx> psi(N, cx(0.0, 0.0));
+    for (const Op &op : plan.ops) {
+        if (op.type == OP_STATS) {
+            if (probs)
+                for (uint64_t i = 0; i < N; i++) probs[(uint64_t)op.q0 * N + i] = std::norm(psi[i]);
+            continue;
+        }
+        emulate_op(plan, op, c->n, psi.data());
+    }
+    if (cycle_row)
+        for (size_t t = 0; t < plan.cycle_row.size(); t++) cycle_row[t] = plan.cycle_row[t];
+    return SV_OK;
+}
+
 extern "C" sv_status sv_host_plan_describe(const sv_circuit *c, sv_dtype dt, const sv_opts *opts,
                                            int from_zero, char *buf, int64_t cap) {
     Plan plan;

@@ -206,6 +206,7 @@ enum OpType : int32_t {
     OP_ADJ_REGTILE,         // adjoint register-tile program (phi and mu)
     OP_CKPT_STORE,          // copy the state to checkpoint q0
     OP_CKPT_LOAD,           // overwrite the state with checkpoint q0
+    OP_STATS,               // statistics pass over the state into row q0
 };
 
 struct Op {
@@ -222,6 +223,8 @@ struct Plan {
     std::vector<Op> ops;
     std::vector<Op> bops;        // adjoint: backward sweep sequence
     std::vector<int> slot_param; // adjoint: parameter index of each slot
+    std::vector<int> cycle_row;  // per-cycle statistics: the row (OP_STATS
+                                 // q0) holding the statistics of cycle t
     int ncheckpoints = 0;
     std::vector<uint8_t> prog;   // host copy of all tile programs
     void *dprog = nullptr;       // device copy
@@ -272,6 +275,12 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan);
 sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int checkpoint_c,
                              Plan *plan);
 double state_bytes(int n, int dtype);
+// Sweeps of c from |0..0> with a statistics pass (OP_STATS) wherever the
+// state's probabilities are those after a cycle: dense gates never cross a
+// cycle's end, diagonal gates may (they leave every |psi_x|^2 unchanged), and
+// cycles whose gates are all diagonal share the previous cycle's row.
+// Modes: REGTILE (AUTO), SPEC, PLAIN.
+sv_status build_cycle_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan);
 
 // ---------------------------------------------------------------------------
 // state handle
@@ -323,6 +332,11 @@ sv_status upload_plan(sv_state *st, Plan *plan);
 // reductions (reduce.hip)
 sv_status run_probs(sv_state *st, uint64_t begin, uint64_t count, int f64, void *out);
 sv_status run_stats(sv_state *st, const void *psi, sv_stats *out);
+// statistics pass of st's state into res[0..14) without synchronising; part
+// holds up to 2048 partial rows of 16 doubles
+sv_status batch_stats_enqueue(sv_state *st, double *part, double *res);
+// the normalised statistics from the 14 combined sums of a 2^n state
+void finish_stats_row(int n, const double *r, sv_stats *out);
 sv_status run_norm(sv_state *st, const void *psi, double *S);
 sv_status run_sample(sv_state *st, const void *psi, int64_t k, uint64_t seed,
                      uint64_t *dev_out);

@@ -1190,6 +1190,98 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
     return SV_OK;
 }
 
+sv_status build_cycle_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
+    for (int64_t i = 1; i < c->ngates; i++)
+        if (c->gates[i].cycle < c->gates[i - 1].cycle)
+            return fail(SV_EINVAL, "per-cycle statistics: gate cycles must be nondecreasing");
+    for (int64_t i = 0; i < c->ngates; i++)
+        if (c->gates[i].cycle < 0) return fail(SV_EINVAL, "per-cycle statistics: negative cycle");
+    int mode = rq.mode == SV_MODE_AUTO ? SV_MODE_REGTILE : rq.mode;
+    if (mode != SV_MODE_REGTILE && mode != SV_MODE_SPEC && mode != SV_MODE_PLAIN)
+        return fail(SV_EINVAL, "per-cycle statistics run register tiles or per-gate sweeps");
+    if (mode == SV_MODE_REGTILE && rq.n < 10) mode = SV_MODE_SPEC;
+    std::vector<SGate> g;
+    SV_TRY(specialise(c, rq.n, &g));
+    plan->n = rq.n;
+    plan->dtype = rq.dtype;
+    const int D = c->ngates ? c->gates[c->ngates - 1].cycle : 0;
+    {
+        Op op;
+        op.bytes = state_bytes(rq.n, rq.dtype);
+        op.type = (mode != SV_MODE_PLAIN && strip_hadamard_layer(&g, rq.n, c)) ? OP_INIT_UNIFORM : OP_INIT_ZERO;
+        plan->ops.push_back(op);
+    }
+    if (mode == SV_MODE_REGTILE) fold_diagonals(&g, rq.n, false, true);
+    // items per cycle (after folding, a dense gate keeps its own cycle)
+    std::vector<std::vector<SGate>> per(D + 1);
+    for (const SGate &s : g) per[c->gates[s.src].cycle].push_back(s);
+    // segments: a cycle with a dense gate closes one (with the diagonal
+    // items pending from the diagonal-only cycles before it); trailing
+    // diagonal items join the last segment, so the final state is the
+    // circuit's output
+    struct Seg { std::vector<SGate> items; int cycle; };
+    std::vector<Seg> segs;
+    std::vector<SGate> pending;
+    for (int t = 0; t <= D; t++) {
+        pending.insert(pending.end(), per[t].begin(), per[t].end());
+        bool dense = false;
+        for (const SGate &s : pending) dense |= s.kind == SG_DENSE;
+        if (dense) {
+            segs.push_back({pending, t});
+            pending.clear();
+        }
+    }
+    if (!pending.empty()) {
+        if (segs.empty()) segs.push_back({pending, 0});
+        else segs.back().items.insert(segs.back().items.end(), pending.begin(), pending.end());
+    }
+    // rows: the initial state (unless a segment closes at cycle 0), then one
+    // per segment; cycle t reports the row of the last segment closing at or
+    // before t
+    int nrows = 0;
+    std::vector<int> row_at(D + 1, -1);
+    auto stats = [&](int first_cycle) {
+        Op op;
+        op.type = OP_STATS;
+        op.q0 = nrows;
+        op.bytes = state_bytes(rq.n, rq.dtype);
+        plan->ops.push_back(op);
+        row_at[first_cycle] = nrows++;
+    };
+    if (segs.empty() || segs[0].cycle > 0) stats(0);
+    for (const Seg &sg : segs) {
+        if (mode == SV_MODE_REGTILE) {
+            int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 6 : 5);
+            vb = std::max(1, std::min(vb, rq.dtype == SV_C64 ? 6 : 5));
+            vb = std::min(vb, rq.n - LANE_BITS);
+            auto sweeps = regtile_sweeps(sg.items, rq.n, vb, rq.dtype, rq.budget > 0 ? (double)rq.budget : -1.0, true);
+            std::vector<std::pair<size_t, int>> scales;
+            for (const Sweep &sw : sweeps) emit_regtile(sg.items, sw, vb, rq.n, rq.dtype, plan, &scales);
+            // the sqrt2 powers of the add-only forms are settled within the
+            // segment, so every statistics point sees the true norm
+            assign_scales(plan, scales);
+        } else {
+            PlanRequest r2 = rq;
+            r2.mode = mode;
+            plan_per_gate(c, sg.items, r2, plan);
+        }
+        stats(sg.cycle);
+    }
+    plan->cycle_row.assign(D + 1, 0);
+    int cur = 0;
+    for (int t = 0; t <= D; t++) {
+        if (row_at[t] >= 0) cur = row_at[t];
+        plan->cycle_row[t] = cur;
+    }
+    plan->sweeps = 0;
+    plan->bytes = 0;
+    for (const Op &op : plan->ops) {
+        plan->sweeps++;
+        plan->bytes += op.bytes;
+    }
+    return SV_OK;
+}
+
 sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int checkpoint_c, Plan *plan) {
     std::vector<SGate> g;
     SV_TRY(specialise(c, rq.n, &g));

@@ -160,6 +160,8 @@ static void finish_stats(int n, const double *r, sv_stats *out) {
     }
 }
 
+void finish_stats_row(int n, const double *r, sv_stats *out) { finish_stats(n, r, out); }
+
 sv_status run_stats(sv_state *st, const void *psi, sv_stats *out) {
     double r[16] = {0};
     if (st->dt == SV_C64) SV_TRY((stats_typed<float, true>(st, psi, r)));

@@ -76,6 +76,11 @@ EXPORTS = {
     "sv_probs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                                 ctypes.c_void_p]),
     "sv_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_cycle_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_host_cycle_emulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
     "sv_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p,
                                  ctypes.c_int]),
     "sv_moments_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
@@ -258,6 +263,17 @@ class State:
         check(lib().sv_moments(self.h, ctypes.byref(s)))
         return s.as_dict()
 
+    def cycle_moments(self, circ, mode="auto", tile=0, budget=0, args: Optional[CircuitArgs] = None):
+        """Statistics after every cycle 0..D of circ run from |0..0> (a list
+        of dicts, one per cycle); the state ends as the circuit's output."""
+        a = args or CircuitArgs(circ)
+        o = make_opts(mode, 0, tile, from_zero=True, budget=budget)
+        D = int(circ.gates["cycle"].max()) if circ.ngates else 0
+        out = (Stats * (D + 1))()
+        nc = ctypes.c_int64()
+        check(lib().sv_cycle_moments(self.h, a.ref, ctypes.byref(o), D + 1, out, ctypes.byref(nc)))
+        return [s.as_dict() for s in out[:nc.value]]
+
     def sample(self, k: int, seed: int) -> np.ndarray:
         out = np.zeros(max(k, 1), dtype=np.uint64)
         check(lib().sv_sample(self.h, k, ctypes.c_uint64(seed), _ptr(out), 0))
@@ -352,6 +368,25 @@ def host_emulate(circ, psi: np.ndarray, dtype="c64", mode="auto", k_max=0, tile=
     check(lib().sv_host_emulate(a.ref, C64 if dtype == "c64" else C128, ctypes.byref(o),
                                 1 if from_zero else 0, _ptr(psi)))
     return psi
+
+
+def host_cycle_emulate(circ, dtype="c64", mode="auto", tile=0, budget=0):
+    """(probabilities at each statistics point of the per-cycle plan, rows x
+    2^n; the row reporting each cycle)."""
+    a = CircuitArgs(circ)
+    o = make_opts(mode, 0, tile, from_zero=True, budget=budget)
+    nr = ctypes.c_int64()
+    nc = ctypes.c_int64()
+    dt = C64 if dtype == "c64" else C128
+    rc = lib().sv_host_cycle_emulate(a.ref, dt, ctypes.byref(o), 0, None, None, 0, ctypes.byref(nr),
+                                     ctypes.byref(nc))
+    if rc not in (SV_OK, SV_ERANGE):
+        check(rc)
+    probs = np.zeros((nr.value, 1 << circ.n))
+    rows = np.zeros(nc.value, dtype=np.int32)
+    check(lib().sv_host_cycle_emulate(a.ref, dt, ctypes.byref(o), nr.value, _ptr(probs), _ptr(rows),
+                                      nc.value, None, None))
+    return probs, rows
 
 
 def host_plan_describe(circ, dtype="c64", mode="auto", k_max=0, tile=0, from_zero=True,

@@ -559,3 +559,55 @@ def test_autograd_two_forwards_then_one_backward():
     l1.backward()
     np.testing.assert_allclose(t1.grad.numpy(), 2.0 * g1, atol=1e-9)
     f.close()
+
+
+# ---------------------------------------------------------------------------
+# statistics after every cycle (Sec. IV)
+# ---------------------------------------------------------------------------
+def _check_cycle_series(got, want, dtype, unif=True):
+    # unif=False: the uniform cross entropy (mean ln p over all x) is not
+    # compared; it is dominated by probabilities at the rounding-residue
+    # level where a state has exact zeros in exact arithmetic
+    assert len(got) == len(want)
+    tol = 1e-10 if dtype == "c128" else 1e-5
+    rt = 1e-9 if dtype == "c128" else 1e-3
+    for t, (g, w) in enumerate(zip(got, want)):
+        assert abs(g["entropy"] - w["entropy"]) <= tol * max(1.0, abs(w["entropy"])), t
+        if not unif:
+            pass
+        elif math.isinf(w["unif_ce"]):     # exact zeros (early cycles from |0..0>)
+            assert math.isinf(g["unif_ce"]), t
+        else:
+            assert abs(g["unif_ce"] - w["unif_ce"]) <= tol * max(1.0, abs(w["unif_ce"])), t
+        assert abs(g["norm"] - 1.0) < (1e-12 if dtype == "c128" else 1e-5), t
+        np.testing.assert_allclose(g["moments"][:6], w["moments"][:6], rtol=rt, err_msg=str(t))
+
+
+@pytest.mark.parametrize("dtype,mode,tile", [("c64", "auto", 0), ("c64", "regtile", 4), ("c128", "regtile", 0),
+                                             ("c128", "spec", 0), ("c64", "plain", 0)])
+def test_cycle_moments_c1(c1, dtype, mode, tile):
+    circ, ref = c1
+    want = oracle.cycle_stats(circ)
+    st = sv.State(circ.n, dtype)
+    got = st.cycle_moments(circ, mode, tile)
+    _check_cycle_series(got, want, dtype)
+    # the state ends as the circuit's output
+    assert np.linalg.norm(st.amplitudes() - ref) <= TOL[dtype]
+    st.close()
+
+
+def test_cycle_moments_20q_and_every_gate_a_cycle():
+    circ = C.make_circuit(4, 5, 20, seed=120)
+    want = oracle.cycle_stats(circ)
+    st = sv.State(circ.n, "c64")
+    _check_cycle_series(st.cycle_moments(circ), want, "c64")
+    st.close()
+    # random kinds and dense gates, each gate its own cycle, from |0..0>
+    rc = C.random_unitary_circuit(12, 80, seed=121)
+    want = oracle.cycle_stats(rc)
+    st = sv.State(rc.n, "c128")
+    _check_cycle_series(st.cycle_moments(rc, "regtile"), want, "c128", unif=False)
+    st.close()
+    with pytest.raises(sv.SVError) as e:
+        sv.State(12, "c64").cycle_moments(rc, "fused")
+    assert e.value.status == sv.SV_EINVAL

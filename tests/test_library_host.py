@@ -116,3 +116,57 @@ def test_host_plan_rejects_bad_gates():
     bad["param"][0] = 0            # Hadamard cannot be parametrised
     with pytest.raises(sv.SVError):
         sv.host_plan(C.Circuit(n=4, gates=bad, theta=np.zeros(1)), "c64", "spec")
+
+
+# ---------------------------------------------------------------------------
+# per-cycle statistics plan: probabilities at every statistics point
+# ---------------------------------------------------------------------------
+def oracle_cycle_probs(circ):
+    cyc = circ.gates["cycle"]
+    psi = oracle.zero_state(circ.n)
+    out, first = [], 0
+    for t in range(int(cyc.max()) + 1):
+        last = first + int((cyc == t).sum())
+        oracle.apply_circuit(circ, psi, first, last)
+        out.append(oracle.probs(psi))
+        first = last
+    return out
+
+
+@pytest.mark.parametrize("dtype,mode,tile", [("c128", "regtile", 0), ("c128", "regtile", 2), ("c64", "regtile", 6),
+                                             ("c64", "regtile", 3), ("c128", "spec", 0), ("c128", "plain", 0)])
+def test_cycle_plan_replay_paper_circuit(dtype, mode, tile):
+    circ = C.make_circuit(3, 5, 24, seed=12)
+    ref = oracle_cycle_probs(circ)
+    probs, rows = sv.host_cycle_emulate(circ, dtype, mode, tile)
+    assert rows.size == len(ref)
+    tol = 1e-12 if dtype == "c128" else 2e-6
+    for t, p in enumerate(ref):
+        assert np.abs(probs[rows[t]] - p).sum() < tol, t
+    # cycles 1..3 are diagonal: no statistics pass of their own
+    assert (rows[:4] == 0).all()
+    dense = {int(c) for k, c in zip(circ.gates["kind"], circ.gates["cycle"]) if k in (C.SX, C.SY)}
+    if mode == "regtile":
+        assert probs.shape[0] == 1 + len(dense)
+
+
+def test_cycle_plan_replay_every_gate_its_own_cycle():
+    # random kinds, dense U1 gates, CZ on arbitrary pairs; gate i in cycle i
+    circ = C.random_unitary_circuit(11, 90, seed=13)
+    ref = oracle_cycle_probs(circ)
+    for mode in ("regtile", "spec"):
+        probs, rows = sv.host_cycle_emulate(circ, "c128", mode, 0)
+        for t, p in enumerate(ref):
+            assert np.abs(probs[rows[t]] - p).sum() < 1e-12, (mode, t)
+
+
+def test_cycle_plan_rejects_unordered_cycles():
+    circ = C.make_circuit(2, 5, 8, seed=14)
+    g = circ.gates.copy()
+    g["cycle"][3], g["cycle"][-1] = g["cycle"][-1], g["cycle"][3]
+    bad = C.Circuit(n=circ.n, gates=g)
+    with pytest.raises(sv.SVError) as e:
+        sv.host_cycle_emulate(bad, "c128", "regtile", 0)
+    assert e.value.status == sv.SV_EINVAL
+    with pytest.raises(ValueError):
+        oracle.cycle_stats(bad)

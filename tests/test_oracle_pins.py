@@ -355,6 +355,52 @@ def test_stats_bruteforce_small():
 
 
 # --------------------------------------------------------------------------
+# statistics after every cycle (Sec. IV)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("rows,cols,depth,seed", [(4, 4, 25, 1), (3, 5, 12, 7)])
+def test_cycle_stats_diagonal_prefix_and_end(rows, cols, depth, seed):
+    # the first cycles of the Sec. IV circuits are diagonal after the
+    # Hadamard layer: the output distribution is exactly uniform up to cycle
+    # 3 (H = ln N, M_k = 1); the last entry is the circuit's output
+    circ = C.make_circuit(rows, cols, depth, seed=seed)
+    cs = oracle.cycle_stats(circ)
+    n = circ.n
+    assert len(cs) == depth + 1
+    for t in range(4):
+        assert abs(cs[t]["entropy"] - n * math.log(2)) < 1e-12
+        assert abs(cs[t]["unif_ce"] - n * math.log(2)) < 1e-12
+        np.testing.assert_allclose(cs[t]["moments"], 1.0, rtol=1e-12)
+    end = oracle.stats(oracle.probs(oracle.apply_circuit(circ)))
+    assert cs[-1]["entropy"] == end["entropy"]
+    np.testing.assert_array_equal(cs[-1]["moments"], end["moments"])
+    # a later cycle has left the uniform distribution
+    assert cs[-1]["entropy"] < n * math.log(2) - 0.1
+
+
+def test_cycle_stats_clifford_vs_tableau():
+    # Clifford variant (T -> S): after every cycle the distribution is uniform
+    # on 2^r outcomes, r from a stabilizer tableau of that cycle's prefix
+    # (the outcomes outside the support are zero up to rounding residues of
+    # the floating-point evolution, so the support is counted by threshold)
+    circ = C.make_circuit(3, 4, 16, seed=33, clifford=True)
+    n = circ.n
+    cs = oracle.cycle_stats(circ)
+    psi = oracle.zero_state(n)
+    cyc = circ.gates["cycle"]
+    first = 0
+    for t, st in enumerate(cs):
+        last = first + int((cyc == t).sum())
+        oracle.apply_circuit(circ, psi, first, last)
+        first = last
+        r = run_clifford(circ.prefix_cycles(t)).num_random()
+        assert abs(st["entropy"] - r * math.log(2)) < 1e-10, t
+        p = oracle.probs(psi)
+        assert int((p > 0.5 * 2.0 ** -r).sum()) == 2 ** r and p[p <= 0.5 * 2.0 ** -r].max(initial=0) < 1e-25, t
+        for k in range(1, 11):
+            assert abs(st["M%d" % k] / 2.0 ** ((n - r) * (k - 1)) - 1) < 1e-10, (t, k)
+
+
+# --------------------------------------------------------------------------
 # probabilities (Sec. II: p(x) = |<x|psi>|^2)
 # --------------------------------------------------------------------------
 def test_probs_c64_exact_products():
