@@ -249,6 +249,68 @@ def make_circuit(rows: int, cols: int, depth: int, seed: int,
                    cols=cols, depth=depth)
 
 
+# Denser family of App. E: every qubit takes part in exactly one CZ per
+# layer, with periodic boundary conditions.  The four perfect matchings of
+# nearest-neighbour bonds on the R x C torus (horizontal or vertical, bonds
+# starting at even or odd columns / rows) are taken in this rotation, so
+# every bond is used once per four layers (R, C >= 4).
+DENSE_LAYOUT_ORDER: Tuple[Tuple[str, int], ...] = (("H", 0), ("V", 0), ("H", 1), ("V", 1))
+
+
+def dense_layout_pairs(rows: int, cols: int, orient: str, a: int) -> List[Tuple[int, int]]:
+    """CZ pairs (q_low, q_high) of one periodic perfect-matching layout."""
+    out = []
+    if orient == "H":
+        for r in range(rows):
+            for c in range(a, cols, 2):
+                q0, q1 = r * cols + c, r * cols + (c + 1) % cols
+                out.append((min(q0, q1), max(q0, q1)))
+    else:
+        for c in range(cols):
+            for r in range(a, rows, 2):
+                q0, q1 = r * cols + c, ((r + 1) % rows) * cols + c
+                out.append((min(q0, q1), max(q0, q1)))
+    out.sort()
+    return out
+
+
+def make_dense_periodic_circuit(rows: int, cols: int, layers: int, seed: int,
+                                clifford: bool = False) -> Circuit:
+    """One random circuit of the denser family of App. E.
+
+    Cycle 0 is a Hadamard on every qubit.  Layer l = 1..layers is a cycle
+    of single-qubit gates on every qubit followed by a cycle of CZ gates in
+    which every qubit takes part in exactly one CZ (layout
+    DENSE_LAYOUT_ORDER[(l - 1) % 4], periodic boundaries).  The single-qubit
+    gates follow the placement rules of Sec. IV that apply here: the first
+    one on a qubit is T, each later one is drawn uniformly from {T, X^1/2,
+    Y^1/2} minus the previous one on that qubit.  Every gate of layer l has
+    cycle l, so statistics after each cycle are per layer, as depth is
+    counted in App. E.  rows and cols must be even (a perfect matching of
+    the torus in both orientations).
+    """
+    if rows < 2 or cols < 2 or rows % 2 or cols % 2 or layers < 0:
+        raise ValueError("the dense periodic family needs even rows and cols >= 2")
+    n = rows * cols
+    rng = SplitMix64(seed)
+    recs: List[Tuple[int, int, int, int, int, int]] = [(H, q, -1, 0, -1, -1) for q in range(n)]
+    tkind = S if clifford else T
+    last_1q = [-1] * n
+    for l in range(1, layers + 1):
+        for q in range(n):
+            if last_1q[q] < 0:
+                kind = tkind
+            else:
+                options = [k for k in (tkind, SX, SY) if k != last_1q[q]]
+                kind = options[rng.next() >> 63]
+            recs.append((kind, q, -1, l, -1, -1))
+            last_1q[q] = kind
+        orient, a = DENSE_LAYOUT_ORDER[(l - 1) % 4]
+        for (qa, qb) in dense_layout_pairs(rows, cols, orient, a):
+            recs.append((CZ, qa, qb, l, -1, -1))
+    return Circuit(n=n, gates=make_gates(recs), rows=rows, cols=cols, depth=layers)
+
+
 def normal_draws(seed: int, count: int) -> np.ndarray:
     """Standard normal deviates by the Box-Muller transform."""
     g = SplitMix64(seed)

@@ -611,3 +611,20 @@ def test_cycle_moments_20q_and_every_gate_a_cycle():
     with pytest.raises(sv.SVError) as e:
         sv.State(12, "c64").cycle_moments(rc, "fused")
     assert e.value.status == sv.SV_EINVAL
+
+
+def test_dense_periodic_family_cycles():
+    # App. E's denser family: per-layer statistics against the oracle, and the
+    # output state, in both precisions
+    circ = C.make_dense_periodic_circuit(4, 4, 14, seed=130)
+    want = oracle.cycle_stats(circ)
+    ref = oracle.apply_circuit(circ)
+    for dtype in ("c64", "c128"):
+        st = sv.State(circ.n, dtype)
+        _check_cycle_series(st.cycle_moments(circ), want, dtype)
+        assert np.linalg.norm(st.amplitudes() - ref) <= TOL[dtype]
+        st.close()
+    circ = C.make_dense_periodic_circuit(4, 6, 10, seed=131)
+    st = sv.State(circ.n, "c64")
+    _check_cycle_series(st.cycle_moments(circ, "regtile", 5), oracle.cycle_stats(circ), "c64")
+    st.close()

@@ -355,6 +355,65 @@ def test_stats_bruteforce_small():
 
 
 # --------------------------------------------------------------------------
+# denser periodic family (App. E)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("rows,cols,layers,seed", [(4, 4, 12, 1), (2, 6, 9, 2), (4, 6, 8, 3), (6, 4, 5, 4)])
+def test_dense_periodic_rules(rows, cols, layers, seed):
+    circ = C.make_dense_periodic_circuit(rows, cols, layers, seed)
+    g = circ.gates
+    n = rows * cols
+
+    def neighbours(a, b):
+        ra, ca, rb, cb = a // cols, a % cols, b // cols, b % cols
+        return (ra == rb and (ca - cb) % cols in (1, cols - 1)) or \
+               (ca == cb and (ra - rb) % rows in (1, rows - 1))
+
+    assert (g["kind"][:n] == C.H).all() and (g["cycle"][:n] == 0).all()
+    assert (np.diff(g["cycle"]) >= 0).all()
+    last = [-1] * n
+    bonds_seen = {}
+    for l in range(1, layers + 1):
+        cyc = g[g["cycle"] == l]
+        one = cyc[cyc["kind"] != C.CZ]
+        cz = cyc[cyc["kind"] == C.CZ]
+        # a single-qubit gate on every qubit, listed before the CZ cycle
+        assert sorted(one["q0"].tolist()) == list(range(n))
+        assert (np.nonzero(cyc["kind"] == C.CZ)[0] >= len(one)).all()
+        for rec in one:
+            q, k = int(rec["q0"]), int(rec["kind"])
+            assert k == C.T if last[q] < 0 else (k in (C.T, C.SX, C.SY) and k != last[q])
+            last[q] = k
+        # every qubit in exactly one CZ, between torus neighbours
+        touched = cz["q0"].tolist() + cz["q1"].tolist()
+        assert sorted(touched) == list(range(n))
+        for rec in cz:
+            assert neighbours(int(rec["q0"]), int(rec["q1"]))
+            bonds_seen.setdefault((int(rec["q0"]), int(rec["q1"])), []).append(l)
+    if rows >= 4 and cols >= 4 and layers >= 8:
+        # all 2n bonds of the torus, each once per four layers
+        assert len(bonds_seen) == 2 * n
+        for ls in bonds_seen.values():
+            assert all(b - a == 4 for a, b in zip(ls, ls[1:]))
+    with pytest.raises(ValueError):
+        C.make_dense_periodic_circuit(5, 4, 3, 0)
+
+
+def test_dense_periodic_first_layer_is_diagonal():
+    # layer 1 is T on every qubit and a CZ cycle: the distribution is still
+    # exactly uniform after it; the Clifford variant follows the tableau
+    circ = C.make_dense_periodic_circuit(4, 4, 10, 5)
+    cs = oracle.cycle_stats(circ)
+    for t in (0, 1):
+        assert abs(cs[t]["entropy"] - 16 * math.log(2)) < 1e-12
+        np.testing.assert_allclose(cs[t]["moments"], 1.0, rtol=1e-12)
+    assert cs[-1]["entropy"] < 16 * math.log(2) - 0.1
+    cl = C.make_dense_periodic_circuit(2, 4, 8, 6, clifford=True)
+    for t, st in enumerate(oracle.cycle_stats(cl)):
+        r = run_clifford(cl.prefix_cycles(t)).num_random()
+        assert abs(st["entropy"] - r * math.log(2)) < 1e-10, t
+
+
+# --------------------------------------------------------------------------
 # statistics after every cycle (Sec. IV)
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("rows,cols,depth,seed", [(4, 4, 25, 1), (3, 5, 12, 7)])
