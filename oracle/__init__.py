@@ -39,6 +39,7 @@ def lib():
         L.orc_cross_entropy.argtypes = [i32, P, P, i64, P, P]
         L.orc_cross_entropy.restype = i64
         L.orc_adjoint.argtypes = [i32, P, i64, P, i32, P, i32, P, i64, P, P]
+        L.orc_pair_stats.argtypes = [i32, P, P, i32, f64, f64, P, P]
         L.orc_num_threads.restype = i32
         _lib = L
     return _lib
@@ -178,6 +179,30 @@ def adjoint(circ, samples: np.ndarray):
     if rc:
         raise ValueError("adjoint failed (%d)" % rc)
     return loss.value, grad[:theta.size]
+
+
+PAIR_NAMES = ["norm_a", "norm_b", "overlap_re", "overlap_im", "fidelity", "xent", "unif_ce",
+              "delta_h", "corr", "zero_a", "zero_mass_b"]
+
+
+def pair_stats(a: np.ndarray, b: np.ndarray, nbins: int = 0, zmin: float = -8.0, zmax: float = 4.0):
+    """Pair statistics of the ideal output a and another output b (complex
+    amplitudes of the same size): a dict of PAIR_NAMES, and for nbins > 0 the
+    histogram of z = ln(N p_a) as a (3, nbins + 2) uint64 array (counts,
+    integer masses of p_a and of p_b; slots nbins and nbins + 1 are below and
+    above the range)."""
+    assert a.shape == b.shape
+    n = int(a.size).bit_length() - 1
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    b = np.ascontiguousarray(b, dtype=np.complex128)
+    out = np.zeros(11)
+    hist = np.zeros(3 * (nbins + 2) if nbins > 0 else 1, dtype=np.uint64)
+    rc = lib().orc_pair_stats(n, _ptr(a), _ptr(b), nbins, zmin, zmax, _ptr(out), _ptr(hist))
+    if rc:
+        raise ValueError("pair statistics rejected the input (%d)" % rc)
+    d = dict(zip(PAIR_NAMES, out.tolist()))
+    d["zero_a"] = int(d["zero_a"])
+    return d, (hist.reshape(3, nbins + 2) if nbins > 0 else None)
 
 
 def num_threads() -> int:

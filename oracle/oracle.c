@@ -484,6 +484,134 @@ int orc_adjoint(int n, const int32_t *gates, int64_t ngates, const double *theta
     return 0;
 }
 
+/* ---------------------------------------------------------------------
+ * Pair statistics of an ideal output a and another output b of the same
+ * size (Secs. II and III: the cross entropy difference of an imperfect
+ * implementation, Eq. (5), the fidelity of Eq. (ra), the residual
+ * correlation of App. D).  With p_a, p_b the probabilities, S_a, S_b their
+ * sums and hat p = p / S:
+ *   out[0] S_a            out[1] S_b
+ *   out[2] Re <a|b>       out[3] Im <a|b>
+ *   out[4] fidelity |<a|b>|^2 / (S_a S_b)
+ *   out[5] cross entropy H(hat p_b, hat p_a) = -sum_x hat p_b ln hat p_a
+ *          (Eq. (15) with the other output as p_cl); +inf if b has mass
+ *          where p_a = 0
+ *   out[6] uniform cross entropy of a, -(1/N) sum ln hat p_a (+inf if some
+ *          p_a = 0)
+ *   out[7] Eq. (5) in its instance form sum_x (1/N - hat p_b) ln(1/hat p_a)
+ *          = out[6] - out[5]; NaN if some p_a = 0
+ *   out[8] Pearson correlation of p_a and p_b over the N outcomes (NaN if
+ *          either is constant)
+ *   out[9] number of x with p_a = 0
+ *   out[10] sum of p_b over those x
+ * Sums are Neumaier-compensated over fixed 2^20-element chunks combined in
+ * chunk order.
+ *
+ * Histogram (nbins > 0): z(x) = ln(N p_a(x)) is binned over [zmin, zmax) in
+ * nbins equal bins.  The decision compares p_a with the thresholds
+ * t_j = e^{zmin + j dz} 2^{-n} (dz = (zmax - zmin) / nbins, j = 0..nbins):
+ * bin j when t_j <= p_a < t_{j+1}; slot nbins ("under") when p_a < t_0 or
+ * p_a = 0; slot nbins + 1 ("over") when p_a >= t_nbins.  Per slot s:
+ *   hist[s]                  number of outcomes
+ *   hist[(nbins+2) + s]      sum of floor(p_a 2^62)
+ *   hist[2 (nbins+2) + s]    sum of floor(p_b 2^62)
+ * (integer masses: exact and independent of summation order).  Returns 0,
+ * -1 for a probability >= 4 (whose integer mass does not fit 64 bits) or
+ * -2 for a memory failure.
+ * ------------------------------------------------------------------- */
+int orc_pair_stats(int n, const double *a, const double *b, int nbins, double zmin,
+                   double zmax, double out[11], uint64_t *hist) {
+    const int64_t N = (int64_t)1 << n;
+    const int64_t nch = (N + CHUNK - 1) / CHUNK;
+    enum { Q = 10 };   /* Sa, Sb, ov_re, ov_im, Saa, Sbb, Sab, Sbl, Sl, Sbz */
+    nsum *acc = (nsum *)calloc((size_t)nch * Q, sizeof(nsum));
+    int64_t *zeros = (int64_t *)calloc((size_t)nch, sizeof(int64_t));
+    double *thr = (double *)malloc(sizeof(double) * (size_t)(nbins > 0 ? nbins + 1 : 1));
+    if (!acc || !zeros || !thr) { free(acc); free(zeros); free(thr); return -2; }
+    const double dz = nbins > 0 ? (zmax - zmin) / nbins : 0.0;
+    for (int j = 0; j <= nbins && nbins > 0; j++) thr[j] = ldexp(exp(zmin + j * dz), -n);
+    const int nslot = nbins + 2;
+    if (nbins > 0) memset(hist, 0, sizeof(uint64_t) * 3 * (size_t)nslot);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(|: bad)
+    for (int64_t c = 0; c < nch; c++) {
+        nsum *s = acc + Q * c;
+        int64_t end = (c + 1) * CHUNK < N ? (c + 1) * CHUNK : N;
+        for (int64_t j = c * CHUNK; j < end; j++) {
+            const double ar = a[2 * j], ai = a[2 * j + 1], br = b[2 * j], bi = b[2 * j + 1];
+            const double pa = ar * ar + ai * ai, pb = br * br + bi * bi;
+            nadd(&s[0], pa);
+            nadd(&s[1], pb);
+            nadd(&s[2], ar * br + ai * bi);   /* conj(a) b */
+            nadd(&s[3], ar * bi - ai * br);
+            nadd(&s[4], pa * pa);
+            nadd(&s[5], pb * pb);
+            nadd(&s[6], pa * pb);
+            if (pa > 0.0) {
+                const double l = log(pa);
+                nadd(&s[7], pb * l);
+                nadd(&s[8], l);
+            } else {
+                zeros[c]++;
+                nadd(&s[9], pb);
+            }
+            if (nbins > 0) {
+                if (!(pa < 4.0) || !(pb < 4.0)) { bad = 1; continue; }
+                int slot;
+                if (!(pa >= thr[0])) slot = nbins;
+                else if (pa >= thr[nbins]) slot = nbins + 1;
+                else {
+                    int lo = 0, hi = nbins;   /* last j with thr[j] <= pa */
+                    while (hi - lo > 1) {
+                        int mid = (lo + hi) / 2;
+                        if (thr[mid] <= pa) lo = mid; else hi = mid;
+                    }
+                    slot = lo;
+                }
+                const uint64_t wa = (uint64_t)ldexp(pa, 62), wb = (uint64_t)ldexp(pb, 62);
+#pragma omp atomic
+                hist[slot] += 1;
+#pragma omp atomic
+                hist[nslot + slot] += wa;
+#pragma omp atomic
+                hist[2 * nslot + slot] += wb;
+            }
+        }
+    }
+    nsum t[Q];
+    memset(t, 0, sizeof t);
+    int64_t z = 0;
+    for (int64_t c = 0; c < nch; c++) {
+        for (int i = 0; i < Q; i++) nadd(&t[i], nval(&acc[Q * c + i]));
+        z += zeros[c];
+    }
+    free(acc);
+    free(zeros);
+    free(thr);
+    if (bad) return -1;
+    const double Nd = (double)N;
+    const double Sa = nval(&t[0]), Sb = nval(&t[1]);
+    const double ore = nval(&t[2]), oim = nval(&t[3]);
+    out[0] = Sa;
+    out[1] = Sb;
+    out[2] = ore;
+    out[3] = oim;
+    out[4] = (ore * ore + oim * oim) / (Sa * Sb);
+    const double mass0 = nval(&t[9]);
+    out[5] = mass0 > 0.0 ? INFINITY : log(Sa) - nval(&t[7]) / Sb;
+    out[6] = z ? INFINITY : log(Sa) - nval(&t[8]) / Nd;
+    out[7] = z ? NAN : out[6] - out[5];
+    /* hat p = p / S:  N sum hat pa hat pb - 1 over the product of the
+     * square roots of N sum hat p^2 - 1 */
+    const double cab = Nd * nval(&t[6]) / (Sa * Sb) - 1.0;
+    const double caa = Nd * nval(&t[4]) / (Sa * Sa) - 1.0;
+    const double cbb = Nd * nval(&t[5]) / (Sb * Sb) - 1.0;
+    out[8] = (caa > 0.0 && cbb > 0.0) ? cab / sqrt(caa * cbb) : NAN;
+    out[9] = (double)z;
+    out[10] = mass0;
+    return 0;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

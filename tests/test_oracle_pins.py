@@ -460,6 +460,85 @@ def test_cycle_stats_clifford_vs_tableau():
 
 
 # --------------------------------------------------------------------------
+# pair statistics of two outputs (Eq. (5), Eq. (ra), App. D)
+# --------------------------------------------------------------------------
+def test_pair_stats_self_and_uniform():
+    n = 14
+    N = 1 << n
+    a = C.random_state(n, 140, dtype=np.complex128)
+    st = oracle.stats(oracle.probs(a))
+    d, _ = oracle.pair_stats(a, a)
+    assert abs(d["fidelity"] - 1) < 1e-12 and abs(d["corr"] - 1) < 1e-12
+    assert abs(d["xent"] - st["entropy"]) < 1e-12            # H(p, p) = H(p)
+    assert abs(d["unif_ce"] - st["unif_ce"]) < 1e-12
+    assert abs(d["delta_h"] - (st["unif_ce"] - st["entropy"])) < 1e-12
+    assert abs(d["overlap_re"] - d["norm_a"]) < 1e-12 and abs(d["overlap_im"]) < 1e-13
+    # the uniform output: cross entropy = uniform cross entropy, Delta H = 0
+    # (Eq. (5): the uniform sampler has no advantage), no correlation defined
+    u = np.full(N, 2.0 ** (-n / 2), dtype=np.complex128)
+    d, _ = oracle.pair_stats(a, u)
+    assert abs(d["xent"] - st["unif_ce"]) < 1e-12 and abs(d["delta_h"]) < 1e-12
+    assert math.isnan(d["corr"])
+    # a global phase of b changes the overlap, not the fidelity
+    d2, _ = oracle.pair_stats(a, a * np.exp(0.7j))
+    assert abs(d2["fidelity"] - 1) < 1e-12 and abs(d2["overlap_im"] - math.sin(0.7)) < 1e-12
+
+
+def test_pair_stats_two_level_closed_form():
+    # p_a = (1.5, 0.5, 1.5, ...) / N and p_b = (0.5, 1.5, ...) / N: correlation
+    # -1; H(p_b, p_a) = -(0.5 ln(1.5/N) + 1.5 ln(0.5/N)) / 2; with real
+    # positive amplitudes <a|b> = sqrt(0.75)
+    n = 11
+    N = 1 << n
+    pa = np.where(np.arange(N) % 2 == 0, 1.5, 0.5) / N
+    pb = np.where(np.arange(N) % 2 == 0, 0.5, 1.5) / N
+    d, _ = oracle.pair_stats(np.sqrt(pa).astype(complex), np.sqrt(pb).astype(complex))
+    assert abs(d["corr"] + 1) < 1e-12
+    xe = -(0.5 * math.log(1.5 / N) + 1.5 * math.log(0.5 / N)) / 2
+    assert abs(d["xent"] - xe) < 1e-12
+    assert abs(d["fidelity"] - 0.75) < 1e-12
+    ue = -(math.log(1.5 / N) + math.log(0.5 / N)) / 2
+    assert abs(d["delta_h"] - (ue - xe)) < 1e-12
+    # orthogonal outputs, zeros of p_a carrying mass of p_b
+    e0 = np.zeros(N, complex)
+    e0[0] = 1
+    e1 = np.zeros(N, complex)
+    e1[1] = 1
+    d, _ = oracle.pair_stats(e0, e1)
+    assert d["fidelity"] == 0 and d["xent"] == math.inf and d["zero_a"] == N - 1
+    assert d["zero_mass_b"] == 1.0 and math.isnan(d["delta_h"])
+
+
+def test_pair_histogram_eq_pal_laws():
+    # z = ln(N p_a) of outcomes drawn from p_a (alpha = 1) has the density
+    # e^{2z - e^z}, of uniform outcomes (alpha = 0) e^{z - e^z} (Eq. (pal));
+    # for a Porter-Thomas vector the histogram masses follow the integrals of
+    # those densities over the bins
+    n = 16
+    N = 1 << n
+    a = C.random_state(n, 141, dtype=np.complex128)
+    u = np.full(N, 2.0 ** (-n / 2), dtype=np.complex128)
+    nb, z0, z1 = 24, -8.0, 4.0
+    _, h = oracle.pair_stats(a, u, nb, z0, z1)
+    assert int(h[0].sum()) == N
+    edges = np.linspace(z0, z1, nb + 1)
+    F1 = lambda z: 1 - (1 + np.exp(z)) * np.exp(-np.exp(z))   # alpha = 1
+    F0 = lambda z: 1 - np.exp(-np.exp(z))                     # alpha = 0
+    m_a = h[1, :nb].astype(float) / 2.0 ** 62
+    m_u = h[2, :nb].astype(float) / 2.0 ** 62
+    want_a = np.diff(F1(edges))
+    want_u = np.diff(F0(edges))
+    # multinomial errors of N draws: a few sqrt(w / N)
+    assert np.all(np.abs(m_a - want_a) < 5 * np.sqrt(want_a / N) + 2e-4)
+    assert np.all(np.abs(m_u - want_u) < 5 * np.sqrt(want_u / N) + 2e-4)
+    # counts equal N times the uniform mass up to the floor of each weight
+    assert np.all(np.abs(h[0, :nb] / N - m_u) < 1e-9)
+    # the slots are a partition: masses sum to the floor sums of all weights
+    wa = np.floor(np.ldexp(oracle.probs(a), 62)).astype(np.uint64)
+    assert int(h[1].sum()) == int(sum(int(w) for w in wa))
+
+
+# --------------------------------------------------------------------------
 # probabilities (Sec. II: p(x) = |<x|psi>|^2)
 # --------------------------------------------------------------------------
 def test_probs_c64_exact_products():
