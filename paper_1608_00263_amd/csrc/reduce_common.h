@@ -12,14 +12,19 @@ constexpr int RB = 256;   // threads per workgroup
 
 template <typename T> struct cpx { T re, im; };
 
-// p = re*re + im*im with both products and the sum rounded separately (no
-// contraction); for complex64 input both products are exact in FP64.
+// p = re*re + im*im with both products and the sum rounded separately: the
+// expression is compiled with contraction off (the rounded-operation
+// intrinsics of this toolchain are plain operators, which the default
+// contraction of device code would fuse into fma(re, re, im*im)); for
+// complex64 input both products are exact in FP64.
 __device__ __forceinline__ double prob_of(cpx<float> a) {
-    double r = (double)a.re, i = (double)a.im;
-    return __dadd_rn(__dmul_rn(r, r), __dmul_rn(i, i));
+#pragma clang fp contract(off)
+    const double r = (double)a.re, i = (double)a.im;
+    return r * r + i * i;
 }
 __device__ __forceinline__ double prob_of(cpx<double> a) {
-    return __dadd_rn(__dmul_rn(a.re, a.re), __dmul_rn(a.im, a.im));
+#pragma clang fp contract(off)
+    return a.re * a.re + a.im * a.im;
 }
 __device__ __forceinline__ double prob_of(double p) { return p; }
 
