@@ -140,6 +140,28 @@ typedef struct {
     int64_t zero_count;
 } sv_stats;
 
+/* Statistics of a pair of outputs of the same size: a, the ideal output
+ * p_U, and b, another output (an implementation with errors, one Monte
+ * Carlo trajectory of it, or a circuit with an inserted error).  With
+ * hat p = p / S and N = 2^n:
+ *  norm_a, norm_b  S_a, S_b
+ *  overlap_re/im   <a|b> = sum_x conj(a_x) b_x
+ *  fidelity        |<a|b>|^2 / (S_a S_b) (the alpha of Eq. (ra) for a pure b)
+ *  xent            -sum_x hat p_b ln hat p_a: the cross entropy of Eq. (15)
+ *                  with b as the sampler; +inf if b has mass where p_a = 0
+ *  unif_ce         -(1/N) sum_x ln hat p_a (+inf if some p_a = 0)
+ *  delta_h         Eq. (5), sum_x (1/N - hat p_b) ln(1 / hat p_a)
+ *                  = unif_ce - xent; NaN if some p_a = 0
+ *  corr            Pearson correlation of p_a and p_b over the N outcomes
+ *                  (the residual correlation of App. D); NaN if either is
+ *                  constant
+ *  zero_mass_b     sum of p_b over the x with p_a = 0
+ *  zero_a          number of x with p_a = 0 */
+typedef struct {
+    double norm_a, norm_b, overlap_re, overlap_im, fidelity, xent, unif_ce, delta_h, corr, zero_mass_b;
+    int64_t zero_a;
+} sv_pair;
+
 typedef struct sv_state sv_state;   /* opaque handle */
 
 /* Allocate a 2^n state in device memory owned by the library and set it to
@@ -288,6 +310,24 @@ sv_status sv_sample_from(const double *probs, uint64_t N, const uint64_t *r64,
  * Synchronises. */
 sv_status sv_cross_entropy(sv_state *st, const uint64_t *samples, int64_t k, double norm,
                            double *ce, double *delta_h, int64_t *zero_samples);
+
+/* Pair statistics (sv_pair) of the ideal output a and another output b
+ * (Secs. II and III: Eq. (5), Eq. (ra); App. D), from one read of both
+ * states: FP64 sums per workgroup, combined in a fixed order (Neumaier).
+ * a and b must have the same n, dtype and stream (else SV_EINVAL).
+ * With nbins in 1..1024, hist (host, 3 (nbins + 2) entries) gets the
+ * histogram of z(x) = ln(N p_a(x)) over [zmin, zmax) in nbins equal bins,
+ * then a slot for p_a below the range or 0 and one for p_a at or above it:
+ * hist[s] = number of outcomes in slot s, hist[(nbins + 2) + s] and
+ * hist[2 (nbins + 2) + s] = the sums of floor(p_a 2^62) and floor(p_b 2^62)
+ * over them (exact integers: mass / 2^62 is the probability mass of the
+ * slot under each output, Eq. (pal) at the fidelity of b).  The slot is
+ * decided by comparing p_a with the thresholds e^{zmin + j dz} 2^{-n},
+ * computed once on the host, so it is exact.  SV_ERANGE for a histogram
+ * of an output whose norm is 4 or more (its integer masses would not fit);
+ * nbins = 0 skips the histogram (hist may be NULL).  Synchronises. */
+sv_status sv_pair_stats(sv_state *a, sv_state *b, int32_t nbins, double zmin, double zmax, sv_pair *out,
+                        uint64_t *hist);
 
 /* Gradient of L(theta) = -(1/k) sum_i ln p_theta(x_i) with respect to
  * theta (length c->nparams, host), by the adjoint method: the forward state

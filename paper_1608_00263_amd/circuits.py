@@ -311,6 +311,82 @@ def make_dense_periodic_circuit(rows: int, cols: int, layers: int, seed: int,
     return Circuit(n=n, gates=make_gates(recs), rows=rows, cols=cols, depth=layers)
 
 
+# --- errors (Sec. III and App. D) ----------------------------------------
+PAULIS = (X, Y, Z)
+# the 15 non-identity two-qubit Paulis (first qubit, second qubit), -1 = I
+PAULI_PAIRS: Tuple[Tuple[int, int], ...] = tuple(
+    (a, b) for a in (-1, X, Y, Z) for b in (-1, X, Y, Z) if not (a == -1 and b == -1))
+
+
+def error_counts(circ: Circuit) -> Tuple[int, int]:
+    """(g1, g2): the one-qubit gates (the Hadamard layer included) and the
+    two-qubit gates of a circuit, the counts of Eq. (6)."""
+    k = circ.gates["kind"]
+    g2 = int((k == CZ).sum())
+    return int(k.size) - g2, g2
+
+
+def noisy_trajectory(circ: Circuit, r1: float, r2: float, r_init: float, r_mes: float,
+                     seed: int) -> Tuple[Circuit, int]:
+    """One Monte Carlo trajectory of the depolarizing error model of Sec. III
+    (the simulations behind Figs. 4 and 5): after each one-qubit gate, with
+    probability r1, one of X, Y, Z (r1 / 3 each); after each CZ, with
+    probability r2, one of the 15 non-identity two-qubit Paulis (r2 / 15
+    each); a bit flip of each qubit's initial |0> with probability r_init,
+    written as Z after its cycle-0 Hadamard (H X = Z H); a bit flip before
+    each measurement with probability r_mes, an X after the last gate.
+    Inserted gates carry the cycle of the gate they follow.  Returns the
+    trajectory and the number of inserted Paulis.  The Hadamard layer counts
+    as one-qubit gates.  All draws come from a SplitMix64 stream."""
+    g = SplitMix64(seed)
+    n = circ.n
+    recs: List[Tuple[int, int, int, int, int, int]] = []
+    inserted = 0
+    first_h = [True] * n
+    last_cycle = int(circ.gates["cycle"].max()) if circ.ngates else 0
+    for rec in circ.gates:
+        kind, q0, q1, cyc = int(rec["kind"]), int(rec["q0"]), int(rec["q1"]), int(rec["cycle"])
+        recs.append(tuple(int(v) for v in rec))
+        if kind == CZ:
+            if g.unit() < r2:
+                pa, pb = PAULI_PAIRS[g.below(15)]
+                for pk, q in ((pa, q0), (pb, q1)):
+                    if pk >= 0:
+                        recs.append((pk, q, -1, cyc, -1, -1))
+                        inserted += 1
+            continue
+        if kind == H and cyc == 0 and first_h[q0]:
+            first_h[q0] = False
+            if g.unit() < r_init:
+                recs.append((Z, q0, -1, 0, -1, -1))
+                inserted += 1
+        if g.unit() < r1:
+            recs.append((PAULIS[g.below(3)], q0, -1, cyc, -1, -1))
+            inserted += 1
+    for q in range(n):
+        if g.unit() < r_mes:
+            recs.append((X, q, -1, last_cycle, -1, -1))
+            inserted += 1
+    out = dataclasses.replace(circ, gates=make_gates(recs))
+    return out, inserted
+
+
+def single_error_circuit(circ: Circuit, qubit: int, cycle: int, kind: int) -> Circuit:
+    """The circuit with one Pauli error (X, a bit flip, or Z, a phase flip)
+    on ``qubit`` at the end of ``cycle`` (App. D: an ideal circuit against
+    the same circuit with a single error at one location)."""
+    if kind not in (X, Y, Z):
+        raise ValueError("a single error is a Pauli X, Y or Z")
+    cyc = circ.gates["cycle"]
+    if not (0 <= qubit < circ.n) or cycle < 0 or cycle > int(cyc.max()):
+        raise ValueError("no such location")
+    at = int(np.searchsorted(cyc, cycle, side="right"))   # after the last gate of the cycle
+    err = np.zeros(1, dtype=GATE_DTYPE)
+    err[0] = (kind, qubit, -1, cycle, -1, -1)
+    gates = np.concatenate([circ.gates[:at], err, circ.gates[at:]])
+    return dataclasses.replace(circ, gates=gates)
+
+
 def normal_draws(seed: int, count: int) -> np.ndarray:
     """Standard normal deviates by the Box-Muller transform."""
     g = SplitMix64(seed)

@@ -463,6 +463,41 @@ sv_status sv_cycle_moments(sv_state *st, const sv_circuit *c, const sv_opts *opt
     return SV_OK;
 }
 
+sv_status sv_pair_stats(sv_state *a, sv_state *b, int32_t nbins, double zmin, double zmax, sv_pair *out,
+                        uint64_t *hist) {
+    SV_TRY(check_state(a));
+    SV_TRY(check_state(b));
+    if (!out) return fail(SV_EINVAL, "null output");
+    if (a->n != b->n || a->dt != b->dt) return fail(SV_EINVAL, "pair statistics need two states of one size and dtype");
+    if (a->stream != b->stream) return fail(SV_EINVAL, "pair statistics need two states on one stream");
+    if (nbins < 0 || nbins > 1024) return fail(SV_ERANGE, "nbins out of range 0..1024");
+    if (nbins > 0 && (!hist || !std::isfinite(zmin) || !std::isfinite(zmax) || !(zmin < zmax)))
+        return fail(SV_EINVAL, "a histogram needs an output array and a finite range zmin < zmax");
+    const int n = a->n;
+    std::vector<double> thr((size_t)nbins + 1);
+    const double dz = nbins > 0 ? (zmax - zmin) / nbins : 0.0;
+    for (int j = 0; j <= nbins && nbins > 0; j++) thr[(size_t)j] = std::ldexp(std::exp(zmin + j * dz), -n);
+    double r[16] = {0};
+    SV_TRY(run_pair_stats(a, b, nbins, thr.data(), r, hist));
+    const double N = std::ldexp(1.0, n);
+    const double Sa = r[0], Sb = r[1];
+    if (nbins > 0 && !(Sa < 4.0 && Sb < 4.0))
+        return fail(SV_ERANGE, "sv_pair_stats: a norm of 4 or more has no 64-bit integer histogram masses");
+    out->norm_a = Sa;
+    out->norm_b = Sb;
+    out->overlap_re = r[2];
+    out->overlap_im = r[3];
+    out->fidelity = (r[2] * r[2] + r[3] * r[3]) / (Sa * Sb);
+    out->zero_mass_b = r[9];
+    out->zero_a = (int64_t)r[10];
+    out->xent = r[9] > 0.0 ? INFINITY : std::log(Sa) - r[7] / Sb;
+    out->unif_ce = out->zero_a ? INFINITY : std::log(Sa) - r[8] / N;
+    out->delta_h = out->zero_a ? NAN : out->unif_ce - out->xent;
+    const double cab = N * r[6] / (Sa * Sb) - 1.0, caa = N * r[4] / (Sa * Sa) - 1.0, cbb = N * r[5] / (Sb * Sb) - 1.0;
+    out->corr = (caa > 0.0 && cbb > 0.0) ? cab / std::sqrt(caa * cbb) : NAN;
+    return SV_OK;
+}
+
 sv_status sv_probs(sv_state *st, uint64_t begin, uint64_t count, int out_f64, void *dev_out) {
     SV_TRY(check_state(st));
     const uint64_t N = 1ull << st->n;

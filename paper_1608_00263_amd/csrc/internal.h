@@ -349,6 +349,12 @@ sv_status run_sample_from(const double *probs, uint64_t N, const uint64_t *r64,
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
 size_t noalloc_scratch_need(int n, int64_t k);
 sv_status run_stats_sample_noalloc(sv_state *st, sv_stats *stats, int64_t k, uint64_t seed, uint64_t *dev_out);
+// pair statistics of a and b (same n, dtype, stream): the 11 combined sums
+// into sums16 (S_a, S_b, Re, Im <a|b>, sum p_a^2, sum p_b^2, sum p_a p_b,
+// sum p_b ln p_a, sum ln p_a, sum of p_b where p_a = 0, zero count), and
+// with nbins > 0 the 3 (nbins + 2) histogram words into host_hist
+sv_status run_pair_stats(sv_state *a, sv_state *b, int nbins, const double *host_thr, double *sums16,
+                         uint64_t *host_hist);
 sv_status run_cross_entropy(sv_state *st, const void *psi, const uint64_t *dev_samples,
                             int64_t k, double S, double *sum_log, int64_t *zeros);
 

@@ -215,14 +215,143 @@ sv_status run_probs(sv_state *st, uint64_t begin, uint64_t count, int f64, void 
     return SV_OK;
 }
 
-// ---------------------------------------------------------------------------
-// sampler (integer CDF)
-// ---------------------------------------------------------------------------
 // w = floor(p 2^62): the scaling by a power of two is exact and the
 // conversion truncates toward zero.
 __device__ __forceinline__ uint64_t weight_of(double p) {
     return (uint64_t)(p * 4611686018427387904.0);
 }
+
+// ---------------------------------------------------------------------------
+// pair statistics of an ideal output a and another output b
+// ---------------------------------------------------------------------------
+// Per workgroup, in FP64: S_a, S_b, Re and Im of sum conj(a) b, sum p_a^2,
+// sum p_b^2, sum p_a p_b, sum over p_a > 0 of p_b ln p_a and of ln p_a, sum
+// over p_a = 0 of p_b; and the number of p_a = 0.  With nbins > 0, the
+// histogram of z = ln(N p_a): the slot of x is found by comparing p_a with
+// the thresholds thr[0..nbins] (bin j: thr[j] <= p_a < thr[j+1]; nbins:
+// below thr[0] or p_a = 0; nbins + 1: at or above thr[nbins]), and the slot
+// gets the count and the integer masses floor(p 2^62) of both outputs
+// (64-bit integer sums: exact, in any order) in LDS, added to hist at the
+// end.
+constexpr int NPAIR = 10;
+constexpr int MAX_PAIR_BINS = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_pair_stats(const cpx<T> *__restrict__ a, const cpx<T> *__restrict__ b,
+                                                   uint64_t chunk, const double *__restrict__ thr, int nbins,
+                                                   double *__restrict__ part, unsigned long long *__restrict__ hist) {
+    __shared__ double red[4 * NPAIR];
+    __shared__ unsigned zred[4];
+    __shared__ double sthr[MAX_PAIR_BINS + 1];
+    __shared__ unsigned long long sh[3 * (MAX_PAIR_BINS + 2)];
+    const int nslot = nbins + 2;
+    if (nbins > 0) {
+        for (int i = threadIdx.x; i <= nbins; i += RB) sthr[i] = thr[i];
+        for (int i = threadIdx.x; i < 3 * nslot; i += RB) sh[i] = 0ull;
+    }
+    __syncthreads();
+    double acc[NPAIR];
+#pragma unroll
+    for (int i = 0; i < NPAIR; i++) acc[i] = 0.0;
+    unsigned zeros = 0;
+    const uint64_t start = (uint64_t)blockIdx.x * chunk, end = start + chunk;
+    for (uint64_t j = start + threadIdx.x; j < end; j += RB) {
+        const cpx<T> av = a[j], bv = b[j];
+        const double ar = av.re, ai = av.im, br = bv.re, bi = bv.im;
+        const double pa = prob_of(av), pb = prob_of(bv);
+        acc[0] += pa;
+        acc[1] += pb;
+        acc[2] += fma(ar, br, ai * bi);
+        acc[3] += fma(ar, bi, -ai * br);
+        acc[4] = fma(pa, pa, acc[4]);
+        acc[5] = fma(pb, pb, acc[5]);
+        acc[6] = fma(pa, pb, acc[6]);
+        const bool pos = pa > 0.0;
+        const double l = pos ? ln_pos(pa) : 0.0;
+        acc[7] = fma(pb, l, acc[7]);
+        acc[8] += l;
+        acc[9] += pos ? 0.0 : pb;
+        zeros += pos ? 0u : 1u;
+        if (nbins > 0) {
+            int slot;
+            if (!(pa >= sthr[0])) {
+                slot = nbins;
+            } else if (pa >= sthr[nbins]) {
+                slot = nbins + 1;
+            } else {
+                int lo = 0, hi = nbins;   // last j with thr[j] <= p_a
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (sthr[mid] <= pa) lo = mid;
+                    else hi = mid;
+                }
+                slot = lo;
+            }
+            // the host rejects the histogram when a norm reaches 4, so a
+            // weight that would not fit is never reported
+            const unsigned long long wa = pa < 4.0 ? weight_of(pa) : 0ull;
+            const unsigned long long wb = pb < 4.0 ? weight_of(pb) : 0ull;
+            atomicAdd(&sh[slot], 1ull);
+            atomicAdd(&sh[nslot + slot], wa);
+            atomicAdd(&sh[2 * nslot + slot], wb);
+        }
+    }
+    block_sum<double, NPAIR>(acc, red);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    zeros = wave_sum(zeros);
+    if (lane == 0) zred[wave] = zeros;
+    __syncthreads();
+    if (threadIdx.x < NPAIR) part[(uint64_t)blockIdx.x * 16 + threadIdx.x] = red[threadIdx.x];
+    if (threadIdx.x == NPAIR) {
+        const unsigned long long z = (unsigned long long)zred[0] + zred[1] + zred[2] + zred[3];
+        part[(uint64_t)blockIdx.x * 16 + NPAIR] = (double)z;
+    }
+    if (nbins > 0)
+        for (int i = threadIdx.x; i < 3 * nslot; i += RB)
+            if (sh[i]) atomicAdd(&hist[i], sh[i]);
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0ull;
+}
+
+sv_status run_pair_stats(sv_state *a, sv_state *b, int nbins, const double *host_thr, double *sums16,
+                         uint64_t *host_hist) {
+    int nb;
+    uint64_t chunk;
+    stats_grid(a->n, &nb, &chunk);
+    const int nslot = nbins + 2;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_part = 0, o_res = al((size_t)nb * 16 * 8), o_thr = o_res + al(16 * 8),
+                 o_hist = o_thr + al((size_t)(nbins + 1) * 8), need = o_hist + al((size_t)3 * nslot * 8);
+    SV_TRY(a->ws.reserve(need));
+    uint8_t *w = (uint8_t *)a->ws.ptr;
+    double *part = (double *)(w + o_part), *res = (double *)(w + o_res), *thr = (double *)(w + o_thr);
+    auto *hist = (unsigned long long *)(w + o_hist);
+    hipStream_t s = a->stream;
+    if (nbins > 0) {
+        hipLaunchKernelGGL(k_zero_u64, dim3(4), dim3(256), 0, s, hist, 3 * nslot);
+        SV_HIP(hipMemcpyAsync(thr, host_thr, (size_t)(nbins + 1) * 8, hipMemcpyHostToDevice, s));
+    }
+    if (a->dt == SV_C64)
+        hipLaunchKernelGGL(k_pair_stats<float>, dim3(nb), dim3(RB), 0, s, (const cpx<float> *)a->data,
+                           (const cpx<float> *)b->data, chunk, thr, nbins, part, hist);
+    else
+        hipLaunchKernelGGL(k_pair_stats<double>, dim3(nb), dim3(RB), 0, s, (const cpx<double> *)a->data,
+                           (const cpx<double> *)b->data, chunk, thr, nbins, part, hist);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, s, part, nb, NPAIR + 1, res);
+    SV_HIP(hipGetLastError());
+    SV_HIP(hipMemcpyAsync(sums16, res, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (nbins > 0)
+        SV_HIP(hipMemcpyAsync(host_hist, hist, (size_t)3 * nslot * 8, hipMemcpyDeviceToHost, s));
+    SV_HIP(hipStreamSynchronize(s));
+    return SV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sampler (integer CDF)
+// ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i) {
     uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;

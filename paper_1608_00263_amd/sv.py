@@ -62,6 +62,17 @@ class Stats(ctypes.Structure):
         return d
 
 
+class Pair(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("norm_a", "norm_b", "overlap_re", "overlap_im", "fidelity",
+                                               "xent", "unif_ce", "delta_h", "corr", "zero_mass_b")] + \
+               [("zero_a", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["zero_a"] = int(self.zero_a)
+        return d
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "sv_alloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
@@ -87,6 +98,8 @@ EXPORTS = {
                                          ctypes.c_void_p, ctypes.c_int]),
     "sv_moments_sample_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                                  ctypes.c_uint64, ctypes.c_void_p]),
+    "sv_pair_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     "sv_sample_from": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                       ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "sv_cross_entropy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
@@ -311,6 +324,17 @@ class State:
         check(lib().sv_backward(self.h, a.ref, ctypes.byref(o), _ptr(x), x.size, checkpoint_c,
                                 ctypes.byref(loss), _ptr(grad)))
         return loss.value, grad[:circ.nparams]
+
+
+def pair_stats(a: "State", b: "State", nbins: int = 0, zmin: float = -8.0, zmax: float = 4.0):
+    """Pair statistics of the ideal output a and another output b: a dict
+    (sv_pair fields) and, for nbins > 0, the histogram of z = ln(N p_a) as a
+    (3, nbins + 2) uint64 array (counts, integer masses of p_a and p_b)."""
+    out = Pair()
+    hist = np.zeros(3 * (nbins + 2) if nbins > 0 else 1, dtype=np.uint64)
+    check(lib().sv_pair_stats(a.h, b.h, nbins, zmin, zmax, ctypes.byref(out),
+                              _ptr(hist) if nbins > 0 else None))
+    return out.as_dict(), (hist.reshape(3, nbins + 2) if nbins > 0 else None)
 
 
 def sample_from(probs, words, torch=None):

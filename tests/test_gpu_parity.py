@@ -97,10 +97,13 @@ def test_grid_24q_depth40():
 # ---------------------------------------------------------------------------
 # statistics, probabilities
 # ---------------------------------------------------------------------------
-def test_probs_exact_and_ranges():
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_probs_exact_and_ranges(dtype):
+    # p = re*re + im*im, each operation rounded (no fused multiply-add): equal
+    # to the reference bit for bit in both precisions
     n = 14
-    psi = C.random_state(n, 11, dtype=np.complex64)
-    st = sv.State(n, "c64", tensor=torch.from_numpy(psi).to("cuda"))
+    psi = C.random_state(n, 11, dtype=np.complex64 if dtype == "c64" else np.complex128)
+    st = sv.State(n, dtype, tensor=torch.from_numpy(psi).to("cuda"))
     p = st.probs().cpu().numpy()
     np.testing.assert_array_equal(p, oracle.probs(psi))     # exact products, one rounding
     part = st.probs(1000, 77).cpu().numpy()
@@ -628,3 +631,101 @@ def test_dense_periodic_family_cycles():
     st = sv.State(circ.n, "c64")
     _check_cycle_series(st.cycle_moments(circ, "regtile", 5), oracle.cycle_stats(circ), "c64")
     st.close()
+
+
+# ---------------------------------------------------------------------------
+# pair statistics; noisy trajectories (Sec. III); single errors (App. D)
+# ---------------------------------------------------------------------------
+PAIR_FLOATS = ("norm_a", "norm_b", "overlap_re", "overlap_im", "fidelity", "xent", "unif_ce", "delta_h", "corr")
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_pair_stats_identical_input(dtype):
+    n = 16
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    a = C.random_state(n, 160, dtype=npdt)
+    b = C.random_state(n, 161, dtype=npdt)
+    b[:5000] = (0.3 * a[:5000] + b[:5000]).astype(npdt)   # partly correlated
+    sa = sv.State(n, dtype, tensor=torch.from_numpy(a).to("cuda"))
+    sb = sv.State(n, dtype, tensor=torch.from_numpy(b).to("cuda"))
+    got, gh = sv.pair_stats(sa, sb, 48, -9.0, 3.0)
+    want, wh = oracle.pair_stats(a, b, 48, -9.0, 3.0)
+    for k in PAIR_FLOATS:
+        assert abs(got[k] - want[k]) <= 1e-11 * max(1.0, abs(want[k])), k
+    assert got["zero_a"] == want["zero_a"] == 0
+    np.testing.assert_array_equal(gh, wh)            # integer masses: exact
+    # zeros of p_a where b has mass: infinite cross entropy, no Delta H
+    a[[3, 99]] = 0
+    sa2 = sv.State(n, dtype, tensor=torch.from_numpy(a).to("cuda"))
+    got, gh = sv.pair_stats(sa2, sb, 16, -6.0, 2.0)
+    want, wh = oracle.pair_stats(a, b, 16, -6.0, 2.0)
+    assert got["zero_a"] == want["zero_a"] == 2 and math.isinf(got["xent"]) and math.isnan(got["delta_h"])
+    assert abs(got["zero_mass_b"] - want["zero_mass_b"]) <= 1e-15
+    np.testing.assert_array_equal(gh, wh)
+    # statuses
+    sc = sv.State(n - 1, dtype)
+    with pytest.raises(sv.SVError) as e:
+        sv.pair_stats(sa, sc)
+    assert e.value.status == sv.SV_EINVAL
+    with pytest.raises(sv.SVError) as e:
+        sv.pair_stats(sa, sb, 2000)
+    assert e.value.status == sv.SV_ERANGE
+    big = sv.State(n, dtype, tensor=torch.from_numpy((3.0 * a).astype(npdt)).to("cuda"))
+    with pytest.raises(sv.SVError) as e:
+        sv.pair_stats(big, sb, 8)
+    assert e.value.status == sv.SV_ERANGE
+    sv.pair_stats(big, sb)                            # no histogram: fine
+    for st in (sa, sb, sa2, sc, big):
+        st.close()
+
+
+def test_noisy_trajectories_vs_oracle():
+    # Monte Carlo trajectories of the Sec. III error model in one batched
+    # call, each against the ideal output: fidelity, Eq. (5) and correlation
+    # per trajectory against the oracle run with the same insertions
+    circ = C.make_circuit(3, 4, 16, seed=170)
+    r = 0.02
+    trajs = [C.noisy_trajectory(circ, r / 10, r, r, r, 1700 + i)[0] for i in range(24)]
+    ideal = sv.State(circ.n, "c64")
+    ideal.apply(circ, "auto", from_zero=True)
+    states = [sv.State(circ.n, "c64") for _ in trajs]
+    sv.apply_batch(states, trajs)
+    ref_ideal = oracle.apply_circuit(circ)
+    for t, st in zip(trajs, states):
+        got, gh = sv.pair_stats(ideal, st, 24, -8.0, 4.0)
+        want, _ = oracle.pair_stats(ref_ideal, oracle.apply_circuit(t), 24, -8.0, 4.0)
+        for k in ("fidelity", "xent", "delta_h", "corr"):
+            assert abs(got[k] - want[k]) <= 1e-4 * max(1.0, abs(want[k])), k
+        # on the GPU's own amplitudes the oracle agrees bit for bit on the
+        # histogram
+        same, sh = oracle.pair_stats(ideal.amplitudes(), st.amplitudes(), 24, -8.0, 4.0)
+        np.testing.assert_array_equal(gh, sh)
+        st.close()
+    ideal.close()
+
+
+def test_single_error_correlations_vs_oracle():
+    # every location of a single X or Z error (qubit, end of cycle) against
+    # the ideal output
+    # (depth 16: no outcome of the ideal output is a structural zero, which
+    # the GPU keeps exact and the FP64 reference leaves as a rounding residue)
+    circ = C.make_circuit(3, 4, 16, seed=180)
+    locs = [(q, t, k) for k in (C.X, C.Z) for t in range(0, 17, 2) for q in range(12)]
+    errs = [C.single_error_circuit(circ, q, t, k) for q, t, k in locs]
+    ideal = sv.State(circ.n, "c64")
+    ideal.apply(circ, "auto", from_zero=True)
+    states = [sv.State(circ.n, "c64") for _ in errs]
+    sv.apply_batch(states, errs)
+    ref_ideal = oracle.apply_circuit(circ)
+    for (q, t, k), e, st in zip(locs, errs, states):
+        got, _ = sv.pair_stats(ideal, st)
+        want, _ = oracle.pair_stats(ref_ideal, oracle.apply_circuit(e))
+        assert got["zero_a"] == want["zero_a"] == 0
+        for key in ("fidelity", "corr", "delta_h"):
+            assert abs(got[key] - want[key]) <= 1e-4 * max(1.0, abs(want[key])), (q, t, k, key)
+        if k == C.Z and t == 16:
+            assert abs(got["corr"] - 1.0) < 1e-5        # a final phase flip is invisible
+        if k == C.X and t == 0:
+            assert abs(got["fidelity"] - 1.0) < 1e-5    # X on |+> after the Hadamard layer
+        st.close()
+    ideal.close()

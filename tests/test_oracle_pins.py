@@ -539,6 +539,93 @@ def test_pair_histogram_eq_pal_laws():
 
 
 # --------------------------------------------------------------------------
+# error models (Sec. III) and single errors (App. D)
+# --------------------------------------------------------------------------
+def test_noisy_trajectory_rules():
+    circ = C.make_circuit(4, 4, 12, seed=150)
+    g1, g2 = C.error_counts(circ)
+    n = circ.n
+    t0, k0 = C.noisy_trajectory(circ, 0.0, 0.0, 0.0, 0.0, 1)
+    assert k0 == 0 and np.array_equal(t0.gates, circ.gates)
+    # every location fires: a Pauli after each one-qubit gate, one or two
+    # after each CZ, Z after each Hadamard of cycle 0, X before measurement
+    t1, k1 = C.noisy_trajectory(circ, 1.0, 1.0, 1.0, 1.0, 2)
+    kinds = t1.gates["kind"]
+    paulis = np.isin(kinds, (C.X, C.Y, C.Z))
+    assert int(paulis.sum()) == k1 and k1 >= g1 + g2 + 2 * n
+    assert (np.diff(t1.gates["cycle"]) >= 0).all()
+    i = 0
+    g = t1.gates
+    for rec in circ.gates:
+        assert tuple(g[i]) == tuple(rec)
+        i += 1
+        if rec["kind"] == C.CZ:
+            j = i
+            while j < len(g) and g["kind"][j] in (C.X, C.Y, C.Z) and g["q0"][j] in (rec["q0"], rec["q1"]):
+                j += 1
+            assert 1 <= j - i <= 2
+            i = j
+        else:
+            extra = 2 if (rec["kind"] == C.H and rec["cycle"] == 0) else 1
+            assert g["kind"][i] == C.Z if extra == 2 else True
+            i += extra
+    assert (g["kind"][i:] == C.X).all() and sorted(g["q0"][i:].tolist()) == list(range(n))
+    # rates and the uniform choice among the 15 two-qubit Paulis
+    r = 0.3
+    fired1 = fired2 = 0
+    pairs = np.zeros(15)
+    for sd in range(200):
+        tr, _ = C.noisy_trajectory(circ, r, r, 0.0, 0.0, 1000 + sd)
+        gg = tr.gates
+        for j in range(len(gg)):
+            if gg["kind"][j] in (C.X, C.Y, C.Z):
+                continue
+            nxt = [gg["kind"][m] for m in range(j + 1, min(j + 3, len(gg)))
+                   if gg["kind"][m] in (C.X, C.Y, C.Z)]
+            if gg["kind"][j] == C.CZ:
+                q0, q1 = gg["q0"][j], gg["q1"][j]
+                a = b = -1
+                m = j + 1
+                while m < len(gg) and gg["kind"][m] in (C.X, C.Y, C.Z) and gg["q0"][m] in (q0, q1):
+                    if gg["q0"][m] == q0: a = int(gg["kind"][m])
+                    else: b = int(gg["kind"][m])
+                    m += 1
+                if (a, b) != (-1, -1):
+                    fired2 += 1
+                    pairs[C.PAULI_PAIRS.index((a, b))] += 1
+            elif nxt and gg["q0"][j + 1] == gg["q0"][j] and gg["kind"][j + 1] in (C.X, C.Y, C.Z):
+                fired1 += 1
+    for fired, tot in ((fired1, 200 * g1), (fired2, 200 * g2)):
+        assert abs(fired / tot - r) < 5 * math.sqrt(r * (1 - r) / tot)
+    chi2 = float(((pairs - pairs.mean()) ** 2 / pairs.mean()).sum())
+    assert scipy.stats.chi2.sf(chi2, 14) > 1e-4
+
+
+def test_single_error_placement_and_app_d_cases():
+    circ = C.make_circuit(4, 4, 20, seed=151)
+    ideal = oracle.apply_circuit(circ)
+    e = C.single_error_circuit(circ, 5, 7, C.X)
+    cyc = circ.gates["cycle"]
+    at = int((cyc <= 7).sum())
+    assert e.ngates == circ.ngates + 1 and tuple(e.gates[at]) == (C.X, 5, -1, 7, -1, -1)
+    assert np.array_equal(np.delete(e.gates, at), circ.gates)
+    # a phase flip after the last cycle leaves the output distribution as it
+    # is (the measurement is in the computational basis)
+    d, _ = oracle.pair_stats(ideal, oracle.apply_circuit(C.single_error_circuit(circ, 3, 20, C.Z)))
+    assert abs(d["corr"] - 1) < 1e-12 and abs(d["xent"] - oracle.stats(oracle.probs(ideal))["entropy"]) < 1e-12
+    # a bit flip after the Hadamard layer acts on |+> and changes nothing
+    d, _ = oracle.pair_stats(ideal, oracle.apply_circuit(C.single_error_circuit(circ, 9, 0, C.X)))
+    assert abs(d["fidelity"] - 1) < 1e-12
+    # a phase flip there makes the state orthogonal; by the end the output is
+    # nearly uncorrelated with the ideal one (Fig. 3: the average over error
+    # locations is close to uniform)
+    d, _ = oracle.pair_stats(ideal, oracle.apply_circuit(C.single_error_circuit(circ, 9, 0, C.Z)))
+    assert d["fidelity"] < 1e-12 and abs(d["corr"]) < 0.2
+    with pytest.raises(ValueError):
+        C.single_error_circuit(circ, 16, 3, C.X)
+
+
+# --------------------------------------------------------------------------
 # probabilities (Sec. II: p(x) = |<x|psi>|^2)
 # --------------------------------------------------------------------------
 def test_probs_c64_exact_products():
