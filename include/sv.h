@@ -105,12 +105,21 @@ enum {
                                the matrix cores (for comparison)             */
     SV_FLAG_STATE_READY = 4,/* sv_backward: the handle already holds U(theta)
                                |0...0> (sv_apply_circuit of the same circuit
-                               and theta): the forward pass is skipped; only
-                               with checkpoint_c = 0                         */
+                               and theta): the forward pass is skipped; with
+                               checkpoint_c > 0 the checkpoints too, kept by
+                               sv_apply_circuit with SV_FLAG_CHECKPOINTS    */
     SV_FLAG_BATCH_LAUNCHES = 8, /* sv_apply_batch: one captured graph of the
                                ordinary per-instance launches (for comparison) */
-    SV_FLAG_BATCH_PERSISTENT = 16 /* sv_apply_batch: the persistent-kernel
+    SV_FLAG_BATCH_PERSISTENT = 16, /* sv_apply_batch: the persistent-kernel
                                schedule instead of one launch per round      */
+    SV_FLAG_CHECKPOINTS = 32 /* sv_apply_circuit: run U|0...0> as the forward
+                               pass of sv_backward (register tiles of its
+                               width, tile_qubits / sweep_budget as there) and
+                               keep the state copies it takes every
+                               checkpoint_c cycles, so that a following
+                               sv_backward with SV_FLAG_STATE_READY and the
+                               same circuit, theta, options and interval
+                               skips the forward pass                       */
 };
 
 typedef struct {
@@ -124,6 +133,8 @@ typedef struct {
                              register one sweep may spend on gates before a
                              new sweep starts (0 = default, 250 complex64,
                              220 complex128; 20..2000)                       */
+    int32_t checkpoint_c; /* SV_FLAG_CHECKPOINTS: the checkpoint interval of
+                             the sv_backward that will follow (0 = none)     */
 } sv_opts;
 
 /* Output statistics of p_hat = p / S (Secs. II and IV):
@@ -333,12 +344,18 @@ sv_status sv_pair_stats(sv_state *a, sv_state *b, int32_t nbins, double zmin, do
  * theta (length c->nparams, host), by the adjoint method: the forward state
  * is rebuilt by applying the inverse gates (no stored history), with a copy
  * of the forward state in the state's precision (complex64 on the bulk
- * path) kept at the end of every checkpoint_c-th cycle (0 = none) and
- * reloaded on the way back.  The circuit must open with a Hadamard on every
+ * path) kept every checkpoint_c cycles (0 = none): at the end of the first
+ * sweep after which every gate of cycles <= k checkpoint_c has run (the
+ * sweeps are not cut for it), written by that sweep's store; the reverse
+ * of that sweep reads phi from the copy instead of the uncomputed state.  The circuit must open with a Hadamard on every
  * qubit and list its gates in nondecreasing cycle order.  On entry the
  * handle may hold anything, unless opts->flags has SV_FLAG_STATE_READY: then
  * it must hold U(theta)|0...0> already (as left by sv_apply_circuit of the
- * same circuit), the forward pass is skipped, and checkpoint_c must be 0.
+ * same circuit) and the forward pass is skipped; with checkpoint_c > 0 the
+ * checkpoints must have been kept by sv_apply_circuit with
+ * SV_FLAG_CHECKPOINTS, the same circuit, theta, tile_qubits, sweep_budget
+ * and interval, with no call that changes the state in between (else
+ * SV_ESTATE).
  * On return its contents are unspecified (the forward state has been
  * uncomputed).  loss gets L(theta).  The reverse sweeps are register tiles:
  * opts->tile_qubits register qubits (0 = default 5 complex64 / 3

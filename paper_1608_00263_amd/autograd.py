@@ -34,7 +34,11 @@ class _CircuitCrossEntropy(torch.autograd.Function):
         c = circ.with_theta(theta.detach().to("cpu", torch.float64).numpy())
         stamp.last += 1
         stamp.ready = None
-        state.apply(c, "auto", from_zero=True)
+        if checkpoint_c > 0:
+            # the forward pass of the adjoint, keeping its state copies
+            state.forward_checkpoints(c, checkpoint_c)
+        else:
+            state.apply(c, "auto", from_zero=True)
         ce, _, zeros = state.cross_entropy(samples)
         if zeros:
             raise sv.SVError(sv.SV_ESTATE, "a sample has probability 0 under the circuit")
@@ -50,10 +54,11 @@ class _CircuitCrossEntropy(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        # the forward state is reused only while the handle still holds this
-        # forward's output (no later forward, no earlier backward, which
-        # uncomputes it); otherwise the backward recomputes it from |0..0>
-        ready = ctx.checkpoint_c == 0 and ctx.stamp.ready == ctx.gen
+        # the forward state (and its checkpoints) is reused only while the
+        # handle still holds this forward's output (no later forward, no
+        # earlier backward, which uncomputes it); otherwise the backward
+        # recomputes it from |0..0>
+        ready = ctx.stamp.ready == ctx.gen
         ctx.stamp.ready = None
         _, grad = ctx.state.backward(ctx.circ, ctx.samples, checkpoint_c=ctx.checkpoint_c,
                                      state_ready=ready)
@@ -66,11 +71,11 @@ class CircuitCrossEntropy(torch.nn.Module):
     """theta -> L(theta) on fixed samples, differentiable by the adjoint method.
 
     circ: a parametrised circuit (its theta is replaced by the input);
-    samples: uint64 bit-strings; checkpoint_c: 0 reuses the forward state for
-    the backward pass (while the module's state still holds that forward's
-    output; after another forward or backward it is recomputed), c > 0
-    recomputes it with a state copy kept every c cycles.  The module owns one
-    GPU state of the circuit's size.
+    samples: uint64 bit-strings; checkpoint_c: the backward pass reuses the
+    forward state while the module's state still holds that forward's output
+    (after another forward or backward it is recomputed); with c > 0 the
+    forward also keeps a state copy every c cycles, which bounds the drift of
+    the uncomputation.  The module owns one GPU state of the circuit's size.
     """
 
     def __init__(self, circ, samples, dtype: str = "c64", checkpoint_c: int = 0):

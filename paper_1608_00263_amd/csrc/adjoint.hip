@@ -250,8 +250,11 @@ __device__ __forceinline__ double lane_rot_dispatch(cplx<T> (&phi)[NR], cplx<T> 
     return 0.0;
 }
 
+// phi is read from phi_src (the state, or the checkpoint of the state after
+// the forward sweep this one reverses) and written to phi_g.
 template <typename T, int VB>
-__global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi_g, cplx<T> *__restrict__ mu_g,
+__global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi_g, const cplx<T> *__restrict__ phi_src,
+                                                       cplx<T> *__restrict__ mu_g,
                                                        const uint8_t *__restrict__ prog, uint64_t ntiles,
                                                        double *__restrict__ gpart, int nslots) {
     constexpr int NR = 1 << VB;
@@ -275,16 +278,17 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
     const uint64_t loff = (uint64_t)(lane & 15) | ((uint64_t)((lane >> 4) & 1) << l4) |
                           ((uint64_t)((lane >> 5) & 1) << l5);
     cplx<T> phi[NR], mu[NR];
+    cplx<T> *const phi_in = const_cast<cplx<T> *>(phi_src);
     if (rows) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            phi[r] = gload<T>(uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r))) + lane);
+            phi[r] = gload<T>(uniform_ptr(phi_in + (base + reg_offset<VB>(bq, r))) + lane);
             mu[r] = gload<T>(uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r))) + lane);
         }
     } else {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            phi[r] = gload<T>(uniform_ptr(phi_g + (base + reg_offset<VB>(bq, r))) + loff);
+            phi[r] = gload<T>(uniform_ptr(phi_in + (base + reg_offset<VB>(bq, r))) + loff);
             mu[r] = gload<T>(uniform_ptr(mu_g + (base + reg_offset<VB>(bq, r))) + loff);
         }
     }
@@ -514,6 +518,27 @@ static unsigned ggrid(uint64_t items) {
     return (unsigned)(g < cap ? (g ? g : 1) : cap);
 }
 
+// Checkpoint i of a plan in the handle's checkpoint workspace.
+template <typename T>
+static cplx<T> *ckpt_ptr(sv_state *st, int i) {
+    const size_t one = ((size_t)(1ull << st->n) * sizeof(cplx<T>) + 255) & ~(size_t)255;
+    return (cplx<T> *)((uint8_t *)st->ws_ck.ptr + (size_t)i * one);
+}
+
+// The forward sweeps of an adjoint plan from |0..0>, each checkpoint written
+// by the store of the sweep after which it falls.
+template <typename T>
+static sv_status forward_typed(sv_state *st, const Plan &plan) {
+    const size_t one = ((size_t)(1ull << st->n) * sizeof(cplx<T>) + 255) & ~(size_t)255;
+    if (plan.ncheckpoints) SV_TRY(st->ws_ck.reserve(one * (size_t)plan.ncheckpoints));
+    for (const Op &op : plan.ops) {
+        void *ck = (op.type == OP_REGTILE && op.q1 >= 0) ? (void *)ckpt_ptr<T>(st, op.q1) : nullptr;
+        SV_TRY(launch_op(st, plan, op, st->data, ck));
+    }
+    st->known_zero = false;
+    return SV_OK;
+}
+
 template <typename T>
 static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *samples, int64_t k,
                                 double *loss, double *grad, int nparams, bool state_ready) {
@@ -521,42 +546,31 @@ static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *
     const uint64_t N = 1ull << n;
     hipStream_t s = st->stream;
     const int nslots = (int)plan.slot_param.size();
-    // device scratch: mu | checkpoints (complex64) | samples | gradient partials | slot sums
+    // device scratch: mu | samples | gradient partials | slot sums; the
+    // checkpoints live in their own workspace (they outlive the forward call
+    // that writes them when the state is kept for a later backward)
     int vb = 0;
     for (const Op &op : plan.bops)
         if (op.type == OP_ADJ_REGTILE) vb = op.vbits;
     const uint64_t ntiles = vb ? N >> (LANE_BITS + vb) : 0;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t b_mu = al(N * sizeof(cplx<T>));
-    // checkpoints: complex64 (the state's own precision for complex64; a
-    // complex128 state keeps complex128 copies so that reloading them costs
-    // no accuracy)
-    const size_t b_ck = al(N * sizeof(cplx<T>)) * (size_t)plan.ncheckpoints;
     const size_t b_x = al((size_t)k * 8);
     const size_t b_gp = al((size_t)ntiles * (nslots ? nslots : 1) * 8);
     const uint64_t nchunks = (ntiles + GCHUNK - 1) / GCHUNK;
     const size_t b_gs = al((size_t)(nslots ? nslots : 1) * 8 * (nchunks + 1));
-    SV_TRY(st->ws2.reserve(b_mu + b_ck + b_x + b_gp + b_gs));
+    SV_TRY(st->ws2.reserve(b_mu + b_x + b_gp + b_gs));
     uint8_t *w = (uint8_t *)st->ws2.ptr;
     cplx<T> *mu = (cplx<T> *)w;
-    uint8_t *ck = w + b_mu;
-    uint64_t *dx = (uint64_t *)(ck + b_ck);
+    uint64_t *dx = (uint64_t *)(w + b_mu);
     double *gpart = (double *)((uint8_t *)dx + b_x);
     double *gsum = (double *)((uint8_t *)gpart + b_gp);
     cplx<T> *phi = (cplx<T> *)st->data;
-    auto ckpt = [&](int i) { return (cplx<T> *)(ck + (size_t)i * al(N * sizeof(cplx<T>))); };
 
-    // forward pass from |0..0>, storing checkpoints (skipped when the
-    // handle already holds the output state and no checkpoint is kept)
-    for (const Op &op : plan.ops) {
-        if (state_ready) break;
-        if (op.type == OP_CKPT_STORE) {
-            SV_HIP(hipMemcpyAsync(ckpt(op.q0), phi, N * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
-        } else {
-            SV_TRY(launch_op(st, plan, op, phi));
-        }
-    }
-    st->known_zero = false;
+    // forward pass from |0..0> with its checkpoints (skipped when the handle
+    // already holds the output state, and the checkpoints if any)
+    if (!state_ready) SV_TRY(forward_typed<T>(st, plan));
+    st->ck_key.clear();   // the reverse sweeps uncompute the state
     // loss and lambda
     SV_HIP(hipMemcpyAsync(dx, samples, (size_t)k * 8, hipMemcpyHostToDevice, s));
     double sum_log = 0;
@@ -568,18 +582,16 @@ static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *
     hipLaunchKernelGGL(k_lambda<T>, dim3((unsigned)((k + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, phi, mu,
                        dx, k);
     SV_HIP(hipGetLastError());
-    // backward sweeps
+    // reverse sweeps; the reverse of a sweep that wrote a checkpoint takes
+    // phi from it
     for (const Op &op : plan.bops) {
-        if (op.type == OP_CKPT_LOAD) {
-            SV_HIP(hipMemcpyAsync(phi, ckpt(op.q0), N * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
-            continue;
-        }
+        const cplx<T> *phi_src = op.q1 >= 0 ? ckpt_ptr<T>(st, op.q1) : phi;
         const uint8_t *prog = (const uint8_t *)plan.dprog + op.prog_off;
         const unsigned grid = (unsigned)((ntiles + 3) / 4);
-#define ADJ_CASE(VB)                                                                                     \
-    case VB:                                                                                             \
-        hipLaunchKernelGGL((k_regtile_adj<T, VB>), dim3(grid), dim3(BLOCK), 0, s, phi, mu, prog, ntiles, \
-                           gpart, nslots);                                                               \
+#define ADJ_CASE(VB)                                                                                           \
+    case VB:                                                                                                   \
+        hipLaunchKernelGGL((k_regtile_adj<T, VB>), dim3(grid), dim3(BLOCK), 0, s, phi, phi_src, mu, prog, ntiles, \
+                           gpart, nslots);                                                                     \
         break;
         switch (op.vbits) {
             ADJ_CASE(1) ADJ_CASE(2) ADJ_CASE(3) ADJ_CASE(4) ADJ_CASE(5)
@@ -604,6 +616,47 @@ static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *
     return SV_OK;
 }
 
+// The adjoint plan of (c, opts, checkpoint_c), from the handle's cache.
+static sv_status adjoint_plan(sv_state *st, const sv_circuit *c, const sv_opts *opts, int checkpoint_c,
+                              std::shared_ptr<Plan> *out, std::string *key_out) {
+    PlanRequest rq{};
+    rq.n = st->n;
+    rq.dtype = st->dt;
+    rq.mode = SV_MODE_REGTILE;
+    rq.tile = opts ? opts->tile_qubits : 0;
+    rq.budget = opts ? opts->sweep_budget : 0;
+    if (rq.budget != 0 && (rq.budget < 20 || rq.budget > 2000)) return fail(SV_EINVAL, "sweep_budget must be 0 or 20..2000");
+    rq.from_zero = true;
+    rq.k_max = 1000 + checkpoint_c;   // distinct cache key per checkpoint interval
+    const std::string key = "adj:" + plan_key(c, rq);
+    auto it = st->plans.find(key);
+    if (it != st->plans.end()) {
+        *out = it->second;
+    } else {
+        auto plan = std::make_shared<Plan>();
+        SV_TRY(build_adjoint_plan(c, rq, checkpoint_c, plan.get()));
+        SV_TRY(upload_plan(st, plan.get()));
+        if (st->plans.size() > 64) st->plans.clear();
+        st->plans[key] = plan;
+        *out = plan;
+    }
+    *key_out = key;
+    return SV_OK;
+}
+
+sv_status run_forward_checkpoints(sv_state *st, const sv_circuit *c, const sv_opts *opts) {
+    const int ck = opts ? opts->checkpoint_c : 0;
+    if (ck < 0) return fail(SV_EINVAL, "checkpoint interval must be >= 0");
+    std::shared_ptr<Plan> plan;
+    std::string key;
+    SV_TRY(adjoint_plan(st, c, opts, ck, &plan, &key));
+    st->ck_key.clear();
+    if (st->dt == SV_C64) SV_TRY(forward_typed<float>(st, *plan));
+    else SV_TRY(forward_typed<double>(st, *plan));
+    st->ck_key = key;
+    return SV_OK;
+}
+
 }  // namespace svi
 
 using namespace svi;
@@ -618,28 +671,12 @@ extern "C" sv_status sv_backward(sv_state *st, const sv_circuit *c, const sv_opt
     for (int64_t i = 0; i < k; i++)
         if (samples[i] >= (1ull << st->n)) return fail(SV_ERANGE, "sv_backward: a sample is not an n-bit string");
     const bool ready = opts && (opts->flags & SV_FLAG_STATE_READY);
-    if (ready && checkpoint_c != 0)
-        return fail(SV_EINVAL, "SV_FLAG_STATE_READY needs checkpoint_c = 0 (no forward pass to store them)");
-    PlanRequest rq{};
-    rq.n = st->n;
-    rq.dtype = st->dt;
-    rq.mode = SV_MODE_REGTILE;
-    rq.tile = opts ? opts->tile_qubits : 0;
-    rq.budget = opts ? opts->sweep_budget : 0;
-    if (rq.budget != 0 && (rq.budget < 20 || rq.budget > 2000)) return fail(SV_EINVAL, "sweep_budget must be 0 or 20..2000");
-    rq.from_zero = true;
-    rq.k_max = 1000 + checkpoint_c;   // distinct cache key per checkpoint interval
-    std::string key = "adj:" + plan_key(c, rq);
     std::shared_ptr<Plan> plan;
-    auto it = st->plans.find(key);
-    if (it != st->plans.end()) {
-        plan = it->second;
-    } else {
-        plan = std::make_shared<Plan>();
-        SV_TRY(build_adjoint_plan(c, rq, checkpoint_c, plan.get()));
-        SV_TRY(upload_plan(st, plan.get()));
-        st->plans[key] = plan;
-    }
+    std::string key;
+    SV_TRY(adjoint_plan(st, c, opts, checkpoint_c, &plan, &key));
+    if (ready && plan->ncheckpoints > 0 && st->ck_key != key)
+        return fail(SV_ESTATE, "sv_backward: the handle holds no checkpoints of this circuit and interval (run "
+                               "sv_apply_circuit with SV_FLAG_CHECKPOINTS and the same options first)");
     if (st->dt == SV_C64) return backward_typed<float>(st, *plan, samples, k, loss, grad, c->nparams, ready);
     return backward_typed<double>(st, *plan, samples, k, loss, grad, c->nparams, ready);
 }

@@ -217,6 +217,7 @@ sv_status get_plan(sv_state *st, const sv_circuit *c, PlanRequest rq, std::share
 }
 
 sv_status run_plan(sv_state *st, const Plan &plan) {
+    st->ck_key.clear();
     for (const Op &op : plan.ops) SV_TRY(launch_op(st, plan, op, st->data));
     st->known_zero = false;
     return SV_OK;
@@ -309,6 +310,7 @@ sv_status sv_reset(sv_state *st) {
     // only a buffer the library owns stays |0..0> until the next call: the
     // caller may write an attached buffer at any time
     st->known_zero = st->owned;
+    st->ck_key.clear();
     return SV_OK;
 }
 
@@ -317,12 +319,14 @@ sv_status sv_data(sv_state *st, void **dev_ptr) {
     if (!dev_ptr) return fail(SV_EINVAL, "null output pointer");
     *dev_ptr = st->data;
     st->known_zero = false;   // the caller may write through the pointer
+    st->ck_key.clear();
     return SV_OK;
 }
 
 sv_status sv_apply_circuit(sv_state *st, const sv_circuit *c, const sv_opts *opts) {
     SV_TRY(check_state(st));
     SV_TRY(check_circuit(st, c));
+    if (opts && (opts->flags & SV_FLAG_CHECKPOINTS)) return run_forward_checkpoints(st, c, opts);
     sv_opts eff;
     int explore = -1;
     SV_TRY(effective_opts(st, c, opts, &eff, &explore));
@@ -331,6 +335,7 @@ sv_status sv_apply_circuit(sv_state *st, const sv_circuit *c, const sv_opts *opt
     SV_TRY(get_plan(st, c, make_request(st, &eff), &plan));
     if (explore < 0) return run_plan(st, *plan);
     float ms = 0;
+    st->ck_key.clear();
     SV_TRY(time_plan(st, *plan, st->data, &ms));
     st->known_zero = false;
     Tune &t = st->tunes[tune_key(st, c, from_zero)];
@@ -375,6 +380,7 @@ sv_status sv_apply_circuit_timed(sv_state *st, const sv_circuit *c, const sv_opt
     std::shared_ptr<Plan> plan;
     SV_TRY(get_plan(st, c, make_request(st, &eff), &plan));
     const size_t m = plan->ops.size();
+    st->ck_key.clear();
     std::vector<hipEvent_t> ev(m + 1);
     for (auto &e : ev) SV_HIP(hipEventCreate(&e));
     sv_status rc = SV_OK;
@@ -449,6 +455,7 @@ sv_status sv_cycle_moments(sv_state *st, const sv_circuit *c, const sv_opts *opt
     SV_TRY(st->ws.reserve((size_t)(2048 + nrows) * 16 * sizeof(double)));
     double *part = (double *)st->ws.ptr;
     double *res = part + (size_t)2048 * 16;
+    st->ck_key.clear();
     for (const Op &op : plan->ops) {
         if (op.type == OP_STATS) SV_TRY(batch_stats_enqueue(st, part, res + (size_t)16 * op.q0));
         else SV_TRY(launch_op(st, *plan, op, st->data));

@@ -496,7 +496,10 @@ extern "C" sv_status sv_apply_batch(sv_state **sts, const sv_circuit *cs, int64_
         e = hipMemcpyAsync(host.data(), last->res, host.size() * 8, hipMemcpyDeviceToHost, last->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&herr, last->err, 4, hipMemcpyDeviceToHost, last->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(last->stream);
-    for (int64_t i = 0; i < count; i++) sts[i]->known_zero = false;
+    for (int64_t i = 0; i < count; i++) {
+        sts[i]->known_zero = false;
+        sts[i]->ck_key.clear();
+    }
     if (e != hipSuccess) return hip_fail(e, "ensemble launch");
     if (herr) return fail(SV_EDEVICE, "batch: a dependency wait exceeded its bound");
     for (int64_t i = 0; i < count; i++) finish_stats(&host[16 * i], sts[i]->n, &out[i]);
@@ -569,6 +572,7 @@ static sv_status batch_graph_of_launches(sv_state **sts, const sv_circuit *cs, i
     for (int64_t i = 0; i < count; i++) {
         sts[i]->stream = saved[i];
         sts[i]->known_zero = false;
+        sts[i]->ck_key.clear();
     }
     if (rc != SV_OK) return rc;
     for (int64_t i = 0; i < count; i++) finish_stats(&host[16 * i], sts[i]->n, &out[i]);

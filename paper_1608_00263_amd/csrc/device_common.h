@@ -422,10 +422,12 @@ __device__ __forceinline__ void regtile_op(cplx<T> (&a)[NR], int kind, int arg, 
 }
 
 // One register tile of a sweep: tile index `tile` of the program at prog,
-// processed by the calling wavefront (lane = its lane id).
+// processed by the calling wavefront (lane = its lane id).  ck, when not
+// null, receives a second copy of the stored tile (a checkpoint of the
+// state after the sweep, written from the registers).
 template <typename T, int VB>
 __device__ __forceinline__ void regtile_apply(cplx<T> *__restrict__ psi, const uint8_t *__restrict__ prog,
-                                              uint64_t tile, int lane) {
+                                              uint64_t tile, int lane, cplx<T> *__restrict__ ck = nullptr) {
     constexpr int NR = 1 << VB;
     const cptr<RTHeader> h = (cptr<RTHeader>)prog;
     uint64_t bq[VB];
@@ -526,6 +528,10 @@ __device__ __forceinline__ void regtile_apply(cplx<T> *__restrict__ psi, const u
     } else {
 #pragma unroll
         for (int r = 0; r < NR; r++) gstore<T>(uniform_ptr(psi + (base + reg_offset<VB>(bq, r))) + loff, a[r]);
+    }
+    if (ck) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) gstore<T>(uniform_ptr(ck + (base + reg_offset<VB>(bq, r))) + loff, a[r]);
     }
 }
 

@@ -204,8 +204,6 @@ enum OpType : int32_t {
     OP_REGTILE,             // register-tile program
     OP_LDSTILE,             // LDS-tile program
     OP_ADJ_REGTILE,         // adjoint register-tile program (phi and mu)
-    OP_CKPT_STORE,          // copy the state to checkpoint q0
-    OP_CKPT_LOAD,           // overwrite the state with checkpoint q0
     OP_STATS,               // statistics pass over the state into row q0
 };
 
@@ -217,6 +215,9 @@ struct Op {
     size_t prog_off = 0;    // byte offset in the plan's program buffer
     double bytes = 0;       // algorithmic HBM bytes of this sweep
     int32_t mfma = 0;       // LDSTILE program uses matrix-core blocks
+    // adjoint plans: q1 of a forward REGTILE op = the checkpoint its store
+    // also writes, of an ADJ_REGTILE op = the checkpoint it reads phi from
+    // (-1: none)
 };
 
 struct Plan {
@@ -313,7 +314,11 @@ struct sv_state {
     int device = 0;
     bool known_zero = false;     // contents are |0..0>
     svi::Workspace ws;           // reductions, sampler
-    svi::Workspace ws2;          // adjoint second state / checkpoints
+    svi::Workspace ws2;          // adjoint second state, sample staging
+    svi::Workspace ws_ck;        // adjoint checkpoints
+    std::string ck_key;          // adjoint plan whose forward left its
+                                 // checkpoints in ws_ck and its output in
+                                 // the state (empty: none)
     std::map<std::string, std::shared_ptr<svi::Plan>> plans;
     std::map<std::string, svi::Tune> tunes;   // explore-on-use records
 };
@@ -323,7 +328,8 @@ namespace svi {
 // ---------------------------------------------------------------------------
 // launchers (sweeps.hip)
 // ---------------------------------------------------------------------------
-sv_status launch_op(sv_state *st, const Plan &plan, const Op &op, void *psi);
+// ck (register-tile sweeps only): also store the swept state there
+sv_status launch_op(sv_state *st, const Plan &plan, const Op &op, void *psi, void *ck = nullptr);
 sv_status get_plan(sv_state *st, const sv_circuit *c, PlanRequest rq, std::shared_ptr<Plan> *out);
 sv_status run_plan(sv_state *st, const Plan &plan);
 sv_status launch_init_zero(sv_state *st, void *psi);
@@ -355,6 +361,9 @@ sv_status run_stats_sample_noalloc(sv_state *st, sv_stats *stats, int64_t k, uin
 // with nbins > 0 the 3 (nbins + 2) histogram words into host_hist
 sv_status run_pair_stats(sv_state *a, sv_state *b, int nbins, const double *host_thr, double *sums16,
                          uint64_t *host_hist);
+// sv_apply_circuit with SV_FLAG_CHECKPOINTS: the forward sweeps of the
+// adjoint plan, keeping its checkpoints for a later sv_backward
+sv_status run_forward_checkpoints(sv_state *st, const sv_circuit *c, const sv_opts *opts);
 sv_status run_cross_entropy(sv_state *st, const void *psi, const uint64_t *dev_samples,
                             int64_t k, double S, double *sum_log, int64_t *zeros);
 

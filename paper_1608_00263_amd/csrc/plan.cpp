@@ -1305,47 +1305,48 @@ sv_status build_adjoint_plan(const sv_circuit *c, const PlanRequest &rq, int che
     int vb = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 5 : 3);
     vb = std::max(1, std::min(vb, rq.dtype == SV_C64 ? 5 : 4));
     vb = std::max(1, std::min(vb, rq.n - LANE_BITS - 2));
-    // segments of consecutive gates between checkpoints
-    std::vector<std::vector<SGate>> segs(1);
-    int cur = 0;
-    for (const SGate &s : g) {
-        int cyc = c->gates[s.src].cycle;
-        int seg = (checkpoint_c > 0 && cyc > 0) ? (cyc - 1) / checkpoint_c : 0;
-        while (cur < seg) { segs.emplace_back(); cur++; }
-        segs[cur].push_back(s);
+    // One grouping of the whole circuit: the same budget as the forward
+    // sweeps (the reverse sweeps are VALU-bound too, and fewer of them finish
+    // sooner: complex64, 5x5 depth-30 circuit with 216 parameters, tile 4:
+    // 3.77 ms at 250 against 3.90 ms at 110).
+    const double budget = rq.budget > 0 ? (double)rq.budget : (rq.dtype == SV_C64 ? 250.0 : 220.0);
+    const std::vector<Sweep> sweeps = regtile_sweeps(g, rq.n, vb, rq.dtype, budget, true);
+    const int m = (int)sweeps.size();
+    // Checkpoints at sweep boundaries: checkpoint k is the state after the
+    // first sweep by which every gate of cycles <= k c has run (the sweeps
+    // are not cut for it); it is written by that sweep's store, and the
+    // reverse of that sweep reads phi from it instead of from the
+    // uncomputed state.  No checkpoint after the last sweep (the state
+    // itself), none twice at one boundary.
+    std::vector<int> ck_after(m, -1);
+    int nck = 0;
+    if (checkpoint_c > 0 && m > 1) {
+        int maxc = 0;
+        for (const SGate &s2 : g) maxc = std::max(maxc, (int)c->gates[s2.src].cycle);
+        std::vector<int> last_sweep(maxc + 1, -1);
+        for (int j2 = 0; j2 < m; j2++)
+            for (int it : sweeps[j2].items) {
+                const int cyc = c->gates[g[it].src].cycle;
+                last_sweep[cyc] = std::max(last_sweep[cyc], j2);
+            }
+        for (int t = 1; t <= maxc; t++) last_sweep[t] = std::max(last_sweep[t], last_sweep[t - 1]);
+        for (int k = 1; (int64_t)k * checkpoint_c < maxc; k++) {
+            const int b = last_sweep[k * checkpoint_c];
+            if (b >= 0 && b < m - 1 && ck_after[b] < 0) ck_after[b] = nck++;
+        }
     }
-    while (!segs.empty() && segs.back().empty()) segs.pop_back();
-    const int nseg = (int)segs.size();
-    std::vector<std::vector<RTProgram>> progs(nseg);
-    for (int k = 0; k < nseg; k++) {
-        // the same budget as the forward sweeps: the reverse sweeps are
-        // VALU-bound too, and fewer of them finish sooner (complex64, 5x5
-        // depth-30 circuit with 216 parameters, tile 4: 3.77 ms at 250
-        // against 3.90 ms at 110)
-        const double budget = rq.budget > 0 ? (double)rq.budget : (rq.dtype == SV_C64 ? 250.0 : 220.0);
-        for (const Sweep &sw : regtile_sweeps(segs[k], rq.n, vb, rq.dtype, budget, true)) {
-            progs[k].push_back(build_regtile(segs[k], sw, vb, rq.n));
-            push_regtile(progs[k].back(), rq.n, rq.dtype, OP_REGTILE, &plan->ops, plan);
-        }
-        if (k + 1 < nseg) {
-            Op ck;
-            ck.type = OP_CKPT_STORE;
-            ck.q0 = k;
-            ck.bytes = 2 * state_bytes(rq.n, rq.dtype);
-            plan->ops.push_back(ck);
-        }
+    std::vector<RTProgram> progs;
+    progs.reserve(m);
+    for (int j2 = 0; j2 < m; j2++) {
+        progs.push_back(build_regtile(g, sweeps[j2], vb, rq.n));
+        push_regtile(progs.back(), rq.n, rq.dtype, OP_REGTILE, &plan->ops, plan);
+        plan->ops.back().q1 = ck_after[j2];
+        if (ck_after[j2] >= 0) plan->ops.back().bytes += state_bytes(rq.n, rq.dtype);
     }
-    plan->ncheckpoints = nseg - 1;
-    for (int k = nseg - 1; k >= 0; k--) {
-        for (int i = (int)progs[k].size() - 1; i >= 0; i--)
-            push_regtile(reverse_regtile(progs[k][i]), rq.n, rq.dtype, OP_ADJ_REGTILE, &plan->bops, plan);
-        if (k > 0) {
-            Op ld;
-            ld.type = OP_CKPT_LOAD;
-            ld.q0 = k - 1;
-            ld.bytes = 2 * state_bytes(rq.n, rq.dtype);
-            plan->bops.push_back(ld);
-        }
+    plan->ncheckpoints = nck;
+    for (int j2 = m - 1; j2 >= 0; j2--) {
+        push_regtile(reverse_regtile(progs[j2]), rq.n, rq.dtype, OP_ADJ_REGTILE, &plan->bops, plan);
+        plan->bops.back().q1 = ck_after[j2];
     }
     plan->sweeps = (int64_t)(plan->ops.size() + plan->bops.size());
     plan->bytes = 0;

@@ -116,12 +116,12 @@ __global__ __launch_bounds__(BLOCK) void k_cz(cplx<T> *__restrict__ psi, int a, 
 template <typename T, int VB>
 __global__ __launch_bounds__(BLOCK) void k_regtile(cplx<T> *__restrict__ psi,
                                                    const uint8_t *__restrict__ prog,
-                                                   uint64_t ntiles) {
+                                                   uint64_t ntiles, cplx<T> *__restrict__ ck) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t tile = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
     if (tile >= ntiles) return;
-    regtile_apply<T, VB>(psi, prog, tile, lane);
+    regtile_apply<T, VB>(psi, prog, tile, lane, ck);
 }
 
 // ---------------------------------------------------------------------------
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(BLOCK) void k_ldstile(cplx<T> *__restrict__ psi,
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-static sv_status launch_typed(sv_state *st, const Plan &plan, const Op &op, cplx<T> *psi) {
+static sv_status launch_typed(sv_state *st, const Plan &plan, const Op &op, cplx<T> *psi, cplx<T> *ck) {
     const int n = st->n;
     const uint64_t N = 1ull << n;
     hipStream_t s = st->stream;
@@ -418,7 +418,7 @@ static sv_status launch_typed(sv_state *st, const Plan &plan, const Op &op, cplx
         const uint64_t ntiles = N >> (LANE_BITS + op.vbits);
         const unsigned grid = (unsigned)((ntiles + 3) / 4);
 #define RT_CASE(VB) \
-    case VB: hipLaunchKernelGGL((k_regtile<T, VB>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles); break;
+    case VB: hipLaunchKernelGGL((k_regtile<T, VB>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles, ck); break;
         switch (op.vbits) {
             RT_CASE(1) RT_CASE(2) RT_CASE(3) RT_CASE(4) RT_CASE(5) RT_CASE(6)
         default: return fail(SV_EINVAL, "register tile width out of range");
@@ -459,9 +459,10 @@ static sv_status launch_typed(sv_state *st, const Plan &plan, const Op &op, cplx
     return SV_OK;
 }
 
-sv_status launch_op(sv_state *st, const Plan &plan, const Op &op, void *psi) {
-    if (st->dt == SV_C64) return launch_typed<float>(st, plan, op, (cplx<float> *)psi);
-    return launch_typed<double>(st, plan, op, (cplx<double> *)psi);
+sv_status launch_op(sv_state *st, const Plan &plan, const Op &op, void *psi, void *ck) {
+    if (ck && op.type != OP_REGTILE) return fail(SV_EINVAL, "a checkpoint store needs a register-tile sweep");
+    if (st->dt == SV_C64) return launch_typed<float>(st, plan, op, (cplx<float> *)psi, (cplx<float> *)ck);
+    return launch_typed<double>(st, plan, op, (cplx<double> *)psi, (cplx<double> *)ck);
 }
 
 sv_status launch_init_zero(sv_state *st, void *psi) {

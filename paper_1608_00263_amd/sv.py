@@ -44,7 +44,7 @@ class CCircuit(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("k_max", ctypes.c_int32),
                 ("tile_qubits", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("sweep_budget", ctypes.c_int32)]
+                ("sweep_budget", ctypes.c_int32), ("checkpoint_c", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -174,12 +174,14 @@ FLAG_NO_MFMA = 2
 FLAG_STATE_READY = 4
 FLAG_BATCH_LAUNCHES = 8
 FLAG_BATCH_PERSISTENT = 16
+FLAG_CHECKPOINTS = 32
 
 
-def make_opts(mode="auto", k_max=0, tile=0, from_zero=False, no_mfma=False, flags=0, budget=0) -> Opts:
+def make_opts(mode="auto", k_max=0, tile=0, from_zero=False, no_mfma=False, flags=0, budget=0,
+              checkpoint_c=0) -> Opts:
     m = MODES[mode] if isinstance(mode, str) else int(mode)
     return Opts(m, k_max, tile, (FLAG_FROM_ZERO if from_zero else 0) | (FLAG_NO_MFMA if no_mfma else 0) | flags,
-                budget)
+                budget, checkpoint_c)
 
 
 def _stream_handle(torch):
@@ -223,6 +225,16 @@ class State:
         """Apply circ in place (from |0..0> regardless of contents if from_zero)."""
         a = args or CircuitArgs(circ)
         o = make_opts(mode, k_max, tile, from_zero, no_mfma, budget=budget)
+        check(lib().sv_apply_circuit(self.h, a.ref, ctypes.byref(o)))
+
+    def forward_checkpoints(self, circ, checkpoint_c: int, tile=0, budget=0,
+                            args: Optional[CircuitArgs] = None):
+        """U|0..0> as the forward pass of backward(): the state copies of
+        every checkpoint_c cycles are kept, so that backward(...,
+        checkpoint_c, state_ready=True) with the same circuit and options
+        skips the forward."""
+        a = args or CircuitArgs(circ)
+        o = make_opts("regtile", 0, tile, flags=FLAG_CHECKPOINTS, budget=budget, checkpoint_c=checkpoint_c)
         check(lib().sv_apply_circuit(self.h, a.ref, ctypes.byref(o)))
 
     def apply_timed(self, circ, mode="auto", k_max=0, tile=0, args: Optional[CircuitArgs] = None,
@@ -314,8 +326,9 @@ class State:
     def backward(self, circ, samples: np.ndarray, checkpoint_c: int = 0, mode="auto", k_max=0,
                  tile=0, state_ready=False, budget=0):
         """Loss and adjoint gradient; state_ready=True reuses the output state
-        the handle holds (left by apply() of the same circuit) instead of
-        recomputing it."""
+        the handle holds (left by apply() of the same circuit, or with
+        checkpoint_c > 0 by forward_checkpoints() with the same arguments)
+        instead of recomputing it."""
         a = CircuitArgs(circ)
         o = make_opts(mode, k_max, tile, flags=FLAG_STATE_READY if state_ready else 0, budget=budget)
         x = np.ascontiguousarray(samples, dtype=np.uint64)

@@ -415,9 +415,51 @@ def test_backward_state_ready_matches_full():
     loss_b, g_b = st.backward(circ, xs, state_ready=True)
     assert abs(loss_a - loss_b) < 1e-5
     np.testing.assert_allclose(g_b, g_a, atol=2e-5)
+    # a checkpointed backward on a state without kept checkpoints
+    st.apply(circ, "auto", from_zero=True)
     with pytest.raises(sv.SVError) as e:
         st.backward(circ, xs, checkpoint_c=2, state_ready=True)
-    assert e.value.status == sv.SV_EINVAL
+    assert e.value.status == sv.SV_ESTATE
+    st.close()
+
+
+@pytest.mark.parametrize("dtype,ck", [("c64", 3), ("c64", 5), ("c128", 4)])
+def test_backward_with_kept_checkpoints(dtype, ck):
+    # the forward pass of the adjoint run by sv_apply_circuit, its state
+    # copies kept for the backward; the checkpoints sit at sweep boundaries
+    circ = C.make_circuit(4, 4, 20, seed=83, parametrise=True, theta_seed=84, theta_std=0.05)
+    p0 = oracle.probs(oracle.apply_circuit(circ.with_theta(np.zeros(circ.nparams))))
+    xs = oracle.sample(p0, 4000, 1008)
+    loss0, g0 = oracle.adjoint(circ, xs)
+    tol = 1e-9 if dtype == "c128" else 1e-4
+    st = sv.State(circ.n, dtype)
+    for tile in (0, 3):
+        st.forward_checkpoints(circ, ck, tile=tile)
+        # the forward output is the circuit's output
+        ref = oracle.apply_circuit(circ)
+        assert np.linalg.norm(st.amplitudes() - ref) <= (1e-11 if dtype == "c128" else 1e-4)
+        st.moments()                                  # reads only: the copies stay valid
+        loss, g = st.backward(circ, xs, checkpoint_c=ck, tile=tile, state_ready=True)
+        assert abs(loss - loss0) < tol and np.abs(g - g0).max() < tol, tile
+        # the same from scratch (forward with its checkpoints inside)
+        loss2, g2 = st.backward(circ, xs, checkpoint_c=ck, tile=tile)
+        assert abs(loss2 - loss0) < tol and np.abs(g2 - g0).max() < tol, tile
+    # the copies do not survive a backward (uncomputed state) or another circuit
+    st.forward_checkpoints(circ, ck)
+    st.backward(circ, xs, checkpoint_c=ck, state_ready=True)
+    with pytest.raises(sv.SVError) as e:
+        st.backward(circ, xs, checkpoint_c=ck, state_ready=True)
+    assert e.value.status == sv.SV_ESTATE
+    st.forward_checkpoints(circ, ck)
+    st.apply(circ, "auto", from_zero=True)
+    with pytest.raises(sv.SVError) as e:
+        st.backward(circ, xs, checkpoint_c=ck, state_ready=True)
+    assert e.value.status == sv.SV_ESTATE
+    # a different interval is a different plan
+    st.forward_checkpoints(circ, ck)
+    with pytest.raises(sv.SVError) as e:
+        st.backward(circ, xs, checkpoint_c=ck + 1, state_ready=True)
+    assert e.value.status == sv.SV_ESTATE
     st.close()
 
 
