@@ -44,21 +44,22 @@ inline Mat2<T> to_mat(const M2 &u) {
 constexpr int BLOCK = 256;
 
 // Value of the lane whose index differs in bit B (a wavefront has 64
-// lanes).  Bits 0..3 use DPP lane moves within rows of 16 (quad
-// permutations and row mirrors), bit 4 a ds_swizzle in xor mode (and mask
-// 0x1f, xor mask 16), bit 5 a ds_bpermute.
+// lanes).  Bits 0, 1 and 3 take one DPP lane move within rows of 16 (quad
+// permutations, rotation of the row by 8), bit 2 two (half-row mirror, then
+// quad reverse), bit 4 a ds_swizzle in xor mode (and mask 0x1f, xor mask
+// 16), bit 5 a ds_bpermute.  The last move of bits 0..3 is written as an
+// update with bound_ctrl and a zero old value: every source lane is inside
+// the row and active, so it equals a plain move, and in that form the
+// compiler merges it into a following add or subtract (one instruction).
 template <int B>
 __device__ __forceinline__ int lane_xor_i(int v) {
-    if constexpr (B == 0) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
-    if constexpr (B == 1) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    if constexpr (B == 0) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);   // quad_perm 1,0,3,2
+    if constexpr (B == 1) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);   // quad_perm 2,3,0,1
     if constexpr (B == 2) {   // i ^ 7 (half-row mirror), then i ^ 3 (quad reverse): i ^ 4
         int m = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);
-        return __builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, false);
+        return __builtin_amdgcn_update_dpp(0, m, 0x1B, 0xF, 0xF, true);
     }
-    if constexpr (B == 3) {   // i ^ 15 (row mirror), then i ^ 7 (half-row mirror): i ^ 8
-        int m = __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);
-        return __builtin_amdgcn_mov_dpp(m, 0x141, 0xF, 0xF, false);
-    }
+    if constexpr (B == 3) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, true);   // row_ror 8: i ^ 8
     if constexpr (B == 4) return __builtin_amdgcn_ds_swizzle(v, 0x401F);   // lane ^ 16
     if constexpr (B == 5) return __shfl_xor(v, 32, 64);
     return v;
@@ -448,10 +449,19 @@ __device__ __forceinline__ void regtile_apply(cplx<T> *__restrict__ psi, const u
 
     cplx<T> a[NR];
     const int gen_n = h->gen_n;
+    // the Clifford forms leave a power of sqrt2 (2^sexp exactly, then
+    // 1/sqrt2) and the tangent-form rotations their cosines: one factor,
+    // applied to the generated value when the sweep generates its input
+    // (the ops are linear), else once after the ops
+    double scale = ldexp(1.0, h->sexp);
+    if (h->shalf) scale *= 0.70710678118654752440;
+    scale *= h->fscale;
     if (gen_n > 0) {
         // the Hadamard layer on |0..0>: every amplitude is 2^{-n/2}
-        T v = (T)ldexp(1.0, -(gen_n / 2));
-        if (gen_n & 1) v *= (T)0.70710678118654752440;
+        double vd = ldexp(1.0, -(gen_n / 2));
+        if (gen_n & 1) vd *= 0.70710678118654752440;
+        const T v = (T)(vd * scale);
+        scale = 1.0;
 #pragma unroll
         for (int r = 0; r < NR; r++) { a[r].re = v; a[r].im = (T)0; }
     } else if (rows) {
@@ -495,27 +505,8 @@ __device__ __forceinline__ void regtile_apply(cplx<T> *__restrict__ psi, const u
             regtile_op<T, NR>(a, ops[o].kind, ops[o].a, ops[o].nterms, ops[o].form, load_mat<T>(ops[o].u), terms, base,
                               lane);
     }
-    // the Clifford forms leave a power of sqrt2: 2^sexp exactly, then 1/sqrt2
-    const int sexp = h->sexp;
-    if (sexp != 0) {
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-            a[r].re = ldexp(a[r].re, sexp);
-            a[r].im = ldexp(a[r].im, sexp);
-        }
-    }
-    if (h->shalf) {
-        const T rs = (T)0.70710678118654752440;
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-            a[r].re *= rs;
-            a[r].im *= rs;
-        }
-    }
-    // the cosines taken out of the tangent-form rotations
-    const double fs = h->fscale;
-    if (fs != 1.0) {
-        const T f = (T)fs;
+    if (scale != 1.0) {
+        const T f = (T)scale;
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             a[r].re *= f;
