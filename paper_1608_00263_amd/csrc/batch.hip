@@ -2,14 +2,13 @@
 // are averages over many random circuit instances), captured once in a HIP
 // graph and replayed.
 //
-// The work of a complex64 register-tile ensemble is cut into items: 16
-// register tiles of one sweep of one instance, or 2^14 amplitudes of its
-// statistics pass.  The items are laid out in one table, instances taken in
-// groups; inside a group the order is (round, instance, chunk), where the
-// r-th round holds the r-th sweep of every instance of the group that has
-// one (then that instance's statistics pass once its sweeps are done).  An
-// item of sweep r of instance i needs every item of the earlier sweeps of i
-// and nothing else.  Two schedules execute the table:
+// The work of a complex64 register-tile ensemble is cut into items: a run of
+// register tiles of one sweep of one instance, or a run of amplitudes of its
+// statistics pass.  The items are laid out in one table in the order (round,
+// instance, chunk), where the r-th round holds the r-th sweep of every
+// instance that has one (then that instance's statistics pass once its
+// sweeps are done).  An item of sweep r of instance i needs every item of the
+// earlier sweeps of i and nothing else.  Two schedules execute the table:
 //
 // * round launches (default): one launch per round, whose grid is every item
 //   of that round of every instance; kernel boundaries order the rounds, so
@@ -22,7 +21,9 @@
 //   table, so the earliest unfinished item can always proceed and the waits
 //   end; the wait is nevertheless bounded and raises an error flag instead
 //   of spinning forever.  On this chip the release of an item costs a
-//   write-back of the XCD's L2, which makes it the slower schedule.
+//   write-back of the XCD's L2, so this schedule takes coarse items (256
+//   tiles, 2^19 amplitudes of statistics) where the round launches take fine
+//   ones (16 tiles, 2^14 amplitudes) for parallelism within a round.
 //
 // Statistics partial rows are combined per instance in chunk order.
 //
@@ -41,12 +42,11 @@
 namespace svi {
 
 
-constexpr int TPI = 16;                 // register tiles per work item
-constexpr int STAT_BITS = 14;           // amplitudes per statistics item: 2^14
-// state bytes per group of instances in the persistent schedule (a group's
-// states are re-read while still in the memory-side cache); the round
-// schedule takes all instances as one group
-constexpr size_t PERSISTENT_GROUP_BYTES = (size_t)128 << 20;
+// register tiles per work item, and log2 of the amplitudes per statistics
+// item (at most; an instance of fewer qubits takes one item), per schedule
+constexpr int TPI_ROUND = 16, TPI_PERSISTENT = 256;
+constexpr int STAT_BITS_ROUND = 14, STAT_BITS_PERSISTENT = 19;
+constexpr int MIN_QUBITS = 14;          // smallest instance of the item tables
 
 struct BRound {                         // one (instance, sweep) run of items
     uint64_t first;                     // table index of its first item
@@ -56,6 +56,8 @@ struct BRound {                         // one (instance, sweep) run of items
     int32_t vb;                         // register qubits; 0 for statistics
     int32_t need;                       // items of the instance that precede it
     int32_t nitems;
+    int32_t tpi;                        // register tiles per item (multiple of 4)
+    int32_t pad;
 };
 
 struct BInst {
@@ -63,6 +65,8 @@ struct BInst {
     double *part;                       // statistics partial rows (16 doubles)
     int32_t n;
     int32_t nchunks;
+    int32_t stat_bits;                  // log2 amplitudes per statistics item
+    int32_t pad;
 };
 
 __global__ void k_zero_u32(unsigned *p, int n) {
@@ -75,15 +79,15 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
            (uint64_t)(unsigned)__builtin_amdgcn_readfirstlane((unsigned)v);
 }
 
-// One item: up to TPI register tiles (TPI / 4 per wave), or one statistics
-// chunk written as a partial row of the instance.
+// One item: up to R.tpi register tiles (R.tpi / 4 per wave), or one
+// statistics chunk written as a partial row of the instance.
 template <int VB>
 __device__ __forceinline__ void run_item(const BRound &R, const BInst &I, uint64_t chunk, int lane, int wave,
                                          double *red, unsigned long long *zred) {
     if (R.vb > 0) {
 #pragma unroll 1
-        for (int i = 0; i < TPI / 4; i++) {
-            const uint64_t tile = chunk * TPI + wave + 4 * i;
+        for (int i = 0; i < R.tpi / 4; i++) {
+            const uint64_t tile = chunk * (uint64_t)R.tpi + wave + 4 * i;
             if (tile >= R.ntiles) break;
             regtile_apply<float, VB>(I.psi, R.prog, tile, lane);
         }
@@ -96,9 +100,10 @@ __device__ __forceinline__ void run_item(const BRound &R, const BInst &I, uint64
     unsigned zeros = 0;
     const double Nd = ldexp(1.0, I.n);
     const gptr<cpx<float>> src =
-        (gptr<cpx<float>>)(reinterpret_cast<cpx<float> *>(I.psi) + (chunk << STAT_BITS));
+        (gptr<cpx<float>>)(reinterpret_cast<cpx<float> *>(I.psi) + (chunk << I.stat_bits));
     constexpr int UNR = 8;   // loads in flight per thread
-    for (int j0 = threadIdx.x; j0 < (1 << STAT_BITS); j0 += BLOCK * UNR) {
+    const int span = 1 << I.stat_bits;   // a multiple of BLOCK * UNR
+    for (int j0 = threadIdx.x; j0 < span; j0 += BLOCK * UNR) {
         cpx<float> buf[UNR];
 #pragma unroll
         for (int v = 0; v < UNR; v++) {
@@ -264,52 +269,46 @@ static sv_status build_ensemble(sv_state **sts, const std::vector<std::shared_pt
     std::vector<int32_t> items_so_far(count, 0);
     // launches of the round schedule: [first item, end item)
     std::vector<std::pair<uint64_t, uint64_t>> launches;
-    const size_t group_bytes = persistent ? PERSISTENT_GROUP_BYTES : SIZE_MAX;
+    const int tpi = persistent ? TPI_PERSISTENT : TPI_ROUND;
+    auto stat_bits = [&](int n) { return std::min(n, persistent ? STAT_BITS_PERSISTENT : STAT_BITS_ROUND); };
     uint64_t total = 0;
-    for (int64_t g0 = 0; g0 < count;) {
-        int64_t g1 = g0;
-        size_t gbytes = 0, grounds = 0;
-        while (g1 < count && (g1 == g0 || gbytes + ((size_t)8 << sts[g1]->n) <= group_bytes)) {
-            gbytes += (size_t)8 << sts[g1]->n;
-            grounds = std::max(grounds, plans[g1]->ops.size() + 1);
-            g1++;
-        }
-        for (size_t r = 0; r < grounds; r++) {
-            const uint64_t round_first = total;
-            for (int64_t i = g0; i < g1; i++) {
-                const Plan &p = *plans[i];
-                BRound R{};
-                R.inst = (int32_t)i;
-                R.need = items_so_far[i];
-                if (r < p.ops.size()) {
-                    const Op &op = p.ops[r];
-                    R.vb = op.vbits;
-                    R.prog = (const uint8_t *)p.dprog + op.prog_off;
-                    R.ntiles = (1ull << sts[i]->n) >> (LANE_BITS + op.vbits);
-                    R.nitems = (int32_t)((R.ntiles + TPI - 1) / TPI);
-                } else if (r == p.ops.size()) {
-                    R.vb = 0;
-                    R.prog = nullptr;
-                    R.ntiles = 1ull << sts[i]->n;
-                    R.nitems = 1 << (sts[i]->n - STAT_BITS);
-                } else {
-                    continue;
-                }
-                R.first = total;
-                total += (uint64_t)R.nitems;
-                items_so_far[i] += R.nitems;
-                rounds.push_back(R);
+    size_t nrounds = 0;
+    for (int64_t i = 0; i < count; i++) nrounds = std::max(nrounds, plans[i]->ops.size() + 1);
+    for (size_t r = 0; r < nrounds; r++) {
+        const uint64_t round_first = total;
+        for (int64_t i = 0; i < count; i++) {
+            const Plan &p = *plans[i];
+            BRound R{};
+            R.inst = (int32_t)i;
+            R.need = items_so_far[i];
+            R.tpi = tpi;
+            if (r < p.ops.size()) {
+                const Op &op = p.ops[r];
+                R.vb = op.vbits;
+                R.prog = (const uint8_t *)p.dprog + op.prog_off;
+                R.ntiles = (1ull << sts[i]->n) >> (LANE_BITS + op.vbits);
+                R.nitems = (int32_t)((R.ntiles + tpi - 1) / tpi);
+            } else if (r == p.ops.size()) {
+                R.vb = 0;
+                R.prog = nullptr;
+                R.ntiles = 1ull << sts[i]->n;
+                R.nitems = 1 << (sts[i]->n - stat_bits(sts[i]->n));
+            } else {
+                continue;
             }
-            if (total > round_first) launches.push_back({round_first, total});
+            R.first = total;
+            total += (uint64_t)R.nitems;
+            items_so_far[i] += R.nitems;
+            rounds.push_back(R);
         }
-        g0 = g1;
+        if (total > round_first) launches.push_back({round_first, total});
     }
     if (rounds.size() >= (1ull << 32)) return fail(SV_ERANGE, "ensemble too large");
     std::vector<uint32_t> item_round(total);
     for (size_t r = 0; r < rounds.size(); r++)
         for (int32_t k = 0; k < rounds[r].nitems; k++) item_round[rounds[r].first + k] = (uint32_t)r;
     size_t part_rows = 0;
-    for (int64_t i = 0; i < count; i++) part_rows += (size_t)1 << (sts[i]->n - STAT_BITS);
+    for (int64_t i = 0; i < count; i++) part_rows += (size_t)1 << (sts[i]->n - stat_bits(sts[i]->n));
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t o_rounds = 0;
     const size_t o_items = al(rounds.size() * sizeof(BRound));
@@ -330,7 +329,8 @@ static sv_status build_ensemble(sv_state **sts, const std::vector<std::shared_pt
     for (int64_t i = 0; i < count; i++) {
         insts[i].psi = (cplx<float> *)sts[i]->data;
         insts[i].n = sts[i]->n;
-        insts[i].nchunks = 1 << (sts[i]->n - STAT_BITS);
+        insts[i].stat_bits = stat_bits(sts[i]->n);
+        insts[i].nchunks = 1 << (sts[i]->n - insts[i].stat_bits);
         insts[i].part = (double *)(m + o_part) + row0 * 16;
         row0 += insts[i].nchunks;
     }
@@ -398,7 +398,7 @@ extern "C" sv_status sv_apply_batch(sv_state **sts, const sv_circuit *cs, int64_
         if (sts[i]->dt != dt) return fail(SV_EINVAL, "batch states must share a dtype");
         if (sts[i]->stream != user) return fail(SV_EINVAL, "batch states must share a stream");
         if (cs[i].n != sts[i]->n) return fail(SV_EINVAL, "circuit / state size mismatch in batch");
-        if (sts[i]->n < STAT_BITS) tables = false;
+        if (sts[i]->n < MIN_QUBITS) tables = false;
     }
     if (opts && opts->mode != SV_MODE_AUTO && opts->mode != SV_MODE_REGTILE) tables = false;
     if (opts && (opts->flags & SV_FLAG_BATCH_LAUNCHES)) tables = false;

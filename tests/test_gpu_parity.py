@@ -354,13 +354,17 @@ def test_batch_schedules_agree_and_repeat():
         assert abs(x["entropy"] - y["entropy"]) < 1e-6
         assert x["entropy"] == z["entropy"] and (x["moments"] == z["moments"]).all()
         assert np.linalg.norm(sa.amplitudes() - sb.amplitudes()) < 1e-5
-    # same width: same tiles and partial rows, so the round and persistent
-    # schedules agree exactly
+    # same width: the same tiles, so the round and persistent schedules give
+    # the same amplitudes bit for bit; their statistics items differ in size
+    # (the partial rows are summed in another grouping), and a replay of one
+    # schedule repeats its statistics exactly
     r4 = sv.apply_batch(a, circs, mode="regtile", tile=5)
     r5 = sv.apply_batch(p, circs, mode="regtile", tile=5, persistent=True)
     r6 = sv.apply_batch(p, circs, mode="regtile", tile=5, persistent=True)
     for u, v, w, sa, sp in zip(r4, r5, r6, a, p):
-        assert u["entropy"] == v["entropy"] == w["entropy"] and (u["moments"] == v["moments"]).all()
+        assert v["entropy"] == w["entropy"] and (v["moments"] == w["moments"]).all()
+        assert abs(u["entropy"] - v["entropy"]) < 1e-12
+        np.testing.assert_allclose(u["moments"], v["moments"], rtol=1e-12)
         assert np.array_equal(sa.amplitudes(), sp.amplitudes())
     for st in a + b + p:
         st.close()
