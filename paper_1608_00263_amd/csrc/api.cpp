@@ -93,7 +93,10 @@ static std::vector<sv_opts> tune_candidates(const sv_state *st) {
         else { add(SV_MODE_REGTILE, 0, 3); add(SV_MODE_REGTILE, 0, 4); add(SV_MODE_REGTILE, 0, 5); }
         add(SV_MODE_FUSED, 2, 0);
         add(SV_MODE_FUSED, 3, 0);
-        add(SV_MODE_TILED, 3, st->dt == SV_C64 ? 12 : 11);
+        // complex64 LDS tiles of dense 8x8 blocks are bound by the FP32 VALU
+        // (32 multiply-adds per amplitude and block, several blocks per tile):
+        // they are not a candidate there
+        if (st->dt != SV_C64) add(SV_MODE_TILED, 3, 11);
     } else {
         add(SV_MODE_SPEC, 0, 0);
     }

@@ -137,7 +137,17 @@ static void emulate_ldstile(const Plan &plan, const Op &op, int n, cx *psi) {
             if (p.kind == LT_BLOCK) {
                 const int k = p.k, d = 1 << k;
                 std::vector<cx> U(d * d);
-                if (p.mfma) {
+                if (p.mfma && !f32) {
+                    // rebuild U from the complex128 fragments: E[row][col] in
+                    // fragment (row / 16, col / 4), lane row % 16 + 16 (col % 4)
+                    const double *f = (const double *)(prog + p.mat_off);
+                    const int ns = d / 2;
+                    auto E = [&](int row, int cl) {
+                        return f[((size_t)(row / 16) * ns + cl / 4) * 64 + row % 16 + 16 * (cl % 4)];
+                    };
+                    for (int a = 0; a < d; a++)
+                        for (int b = 0; b < d; b++) U[a * d + b] = cx(E(2 * a, 2 * b), E(2 * a + 1, 2 * b));
+                } else if (p.mfma) {
                     // rebuild U from the lane-ordered real embedding
                     const float *f = (const float *)(prog + p.mat_off);
                     for (int a = 0; a < d; a++)

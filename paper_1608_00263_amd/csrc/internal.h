@@ -215,6 +215,8 @@ struct Op {
     size_t prog_off = 0;    // byte offset in the plan's program buffer
     double bytes = 0;       // algorithmic HBM bytes of this sweep
     int32_t mfma = 0;       // LDSTILE program uses matrix-core blocks
+    // LDSTILE: q1 = the widest block, q0 = 1 when every block of 4 or 5
+    // qubits runs on the matrix cores (selects the kernel variant)
     // adjoint plans: q1 of a forward REGTILE op = the checkpoint its store
     // also writes, of an ADJ_REGTILE op = the checkpoint it reads phi from
     // (-1: none)

@@ -390,6 +390,9 @@ static std::vector<Sweep> group_sweeps_once(bool lookahead, int nfixed, int nite
             simulate(&fixed, &sw);
             if (sw.items.size() > best.items.size()) best = sw;
         }
+        // an item that fits no sweep (wider than the tile) would never be
+        // taken: no grouping
+        if (best.items.empty()) return {};
         for (int i : best.items) done[i] = 1;
         left -= (int)best.items.size();
         out.push_back(best);
@@ -405,6 +408,7 @@ static std::vector<Sweep> group_sweeps(int nitems, int n, int cap, const std::fu
                                        double budget = 0, int nfixed = LANE_BITS) {
     std::vector<Sweep> a = group_sweeps_once(false, nfixed, nitems, n, cap, diag, qubits, cost, budget);
     std::vector<Sweep> b = group_sweeps_once(true, nfixed, nitems, n, cap, diag, qubits, cost, budget);
+    if (a.empty() || b.empty()) return a.empty() ? b : a;   // empty: some item fits no sweep
     return b.size() < a.size() ? b : a;
 }
 
@@ -932,7 +936,15 @@ static void emit_ldstile(const std::vector<SGate> &g, const std::vector<const Bl
         o.kind = LT_BLOCK;
         o.k = (int)B->qubits.size();
         for (int j = 0; j < o.k; j++) o.pos[j] = local[B->qubits[j]];
-        if (o.k >= 4 && dtype == SV_C64 && !no_mfma) { mfma = true; o.mfma = 1; }
+        // matrix cores for blocks of 4 or 5 qubits in complex64 and of 5 in
+        // complex128 (the FP64 matrix and vector peaks are equal on this chip:
+        // measured, the 16x16 blocks ran as fast or faster on the vector ALU,
+        // the 32x32 blocks twice as fast on the matrix cores), where the tile
+        // holds the columns of one instruction sequence per wave (32 in
+        // complex64, 16 per wave and 64 in all in complex128); the kernel
+        // takes the same rule
+        const bool c64 = dtype == SV_C64;
+        if (o.k >= (c64 ? 4 : 5) && !no_mfma && mbits - o.k >= (c64 ? 5 : 6)) { mfma = true; o.mfma = 1; }
         mats.push_back({ops.size(), block_matrix(g, *B)});
         ops.push_back(o);
     }
@@ -940,12 +952,26 @@ static void emit_ldstile(const std::vector<SGate> &g, const std::vector<const Bl
     size_t hoff = push_struct(&plan->prog, h);
     // matrices in the state precision; matrix-core blocks get their real
     // embedding E[2a + ra][2b + rb] (Ur on ra == rb, -Ui for (0,1), Ui for
-    // (1,0)) laid out as the A operands of v_mfma_f32_32x32x2f32: for M block
-    // mb and step b, lane l holds E[l % 32 + 32 mb][2 b + l / 32]
+    // (1,0)) laid out as A operands: of v_mfma_f32_32x32x2f32 in complex64
+    // (for M block mb and step b, lane l holds E[l % 32 + 32 mb][2 b + l / 32]),
+    // of v_mfma_f64_16x16x4f64 in complex128 (for M block mb and step s, lane
+    // l holds E[l % 16 + 16 mb][4 s + l / 16])
+    auto embed = [](const cd &u, int ra, int rb) { return ra == rb ? u.re : (ra == 0 ? -u.im : u.im); };
     for (auto &pm : mats) {
         size_t off;
         const LTOp &bop = ops[pm.first];
-        if (bop.mfma) {
+        if (bop.mfma && dtype != SV_C64) {
+            const int d = 1 << bop.k, nmb = d / 8, ns = d / 2;
+            std::vector<double> f((size_t)nmb * ns * 64);
+            for (int mb = 0; mb < nmb; mb++)
+                for (int st = 0; st < ns; st++)
+                    for (int l = 0; l < 64; l++) {
+                        const int row = l % 16 + 16 * mb, cl = 4 * st + l / 16;
+                        const cd u = pm.second[(size_t)(row / 2) * d + cl / 2];
+                        f[((size_t)mb * ns + st) * 64 + l] = embed(u, row % 2, cl % 2);
+                    }
+            off = push_bytes(&plan->prog, f.data(), f.size() * sizeof(double));
+        } else if (bop.mfma) {
             const int d = 1 << bop.k, nmb = d / 16;
             std::vector<float> f((size_t)nmb * d * 64);
             for (int mb = 0; mb < nmb; mb++)
@@ -953,7 +979,7 @@ static void emit_ldstile(const std::vector<SGate> &g, const std::vector<const Bl
                     for (int l = 0; l < 64; l++) {
                         const int row = l % 32 + 32 * mb, a = row / 2, ra = row % 2, rb = l / 32;
                         const cd u = pm.second[(size_t)a * d + b];
-                        f[((size_t)mb * d + b) * 64 + l] = (float)(ra == rb ? u.re : (ra == 0 ? -u.im : u.im));
+                        f[((size_t)mb * d + b) * 64 + l] = (float)embed(u, ra, rb);
                     }
             off = push_bytes(&plan->prog, f.data(), f.size() * sizeof(float));
         } else if (dtype == SV_C64) {
@@ -979,8 +1005,12 @@ static void emit_ldstile(const std::vector<SGate> &g, const std::vector<const Bl
     op.prog_off = hoff;
     op.mfma = mfma;
     op.q1 = 0;   // widest block (selects the kernel variant)
+    op.q0 = 1;   // 1: every block of 4 or 5 qubits runs on the matrix cores
     for (const LTOp &o : ops)
-        if (o.kind == LT_BLOCK) op.q1 = std::max(op.q1, o.k);
+        if (o.kind == LT_BLOCK) {
+            op.q1 = std::max(op.q1, o.k);
+            if (o.k >= 4 && !o.mfma) op.q0 = 0;
+        }
     op.bytes = 2 * state_bytes(n, dtype);
     plan->ops.push_back(op);
 }
@@ -1135,8 +1165,13 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
     } else {
         fold_diagonals(&g, rq.n);
         int kmax = rq.k_max > 0 ? std::min(rq.k_max, 5) : 4;
-        std::vector<Block> blocks = fuse_blocks(g, rq.n, kmax);
         int mmax = rq.dtype == SV_C64 ? 13 : 12;
+        // LDS tiles of m qubits gather m - 6 qubits above the lanes: a block
+        // may not be wider than that
+        int m_tiled = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 12 : 11);
+        m_tiled = std::min(std::max(8, std::min(m_tiled, mmax)), rq.n);
+        if (mode != SV_MODE_FUSED) kmax = std::max(1, std::min(kmax, m_tiled - LANE_BITS));
+        std::vector<Block> blocks = fuse_blocks(g, rq.n, kmax);
         if (mode == SV_MODE_FUSED) {
             // one sweep per dense block; diagonal blocks ride along with the
             // next dense block (or the previous one at the end)
@@ -1167,13 +1202,12 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
                 emit_ldstile(g, grp, tile, m, rq.n, rq.dtype, plan, rq.no_mfma);
             }
         } else {
-            int m = rq.tile > 0 ? rq.tile : (rq.dtype == SV_C64 ? 12 : 11);
-            m = std::max(8, std::min(m, mmax));
-            m = std::min(m, rq.n);
+            const int m = m_tiled;
             int cap = m - LANE_BITS;
             auto sweeps = group_sweeps(
                 (int)blocks.size(), rq.n, cap, [&](int i) { return blocks[i].diag; },
                 [&](int i) { return blocks[i].qubits; });
+            if (sweeps.empty() && !blocks.empty()) return fail(SV_EINVAL, "a fused block is wider than the LDS tile");
             for (const Sweep &sw : sweeps) {
                 std::vector<const Block *> items;
                 for (int i : sw.items) items.push_back(&blocks[i]);

@@ -15,8 +15,9 @@
 //    CZ gates anywhere are sign flips evaluated from the index bits;
 //  * LDS tiles: a workgroup stages 2^m amplitudes (qubits 0..5 plus m-6
 //    gathered qubits) in LDS and applies dense 2^k x 2^k blocks to it, on
-//    the VALU for k <= 3 and on the matrix cores (v_mfma_f32_32x32x2f32,
-//    complex product as a real 2x2-block embedding) for k = 4, 5.
+//    the VALU for k <= 3 and on the matrix cores for k = 4, 5 in complex64
+//    (v_mfma_f32_32x32x2f32) and k = 5 in complex128 (v_mfma_f64_16x16x4f64),
+//    the complex product as a real 2x2-block embedding.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -237,20 +238,92 @@ __device__ __forceinline__ void block_mfma(cplx<float> *lds, const LTOp &op,
     }
 }
 
-template <typename T, int MB, int KMAX>
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// Dense 2^K block (K = 5) on the matrix cores, complex128, through
+// v_mfma_f64_16x16x4f64: D(16x16) += A(16x4) B(4x16).  The real embedding E
+// is the one of the complex64 path; M block mb covers rows 16 mb .. 16 mb + 15
+// (output amplitudes 8 mb .. 8 mb + 7), step s covers columns 4 s .. 4 s + 3
+// (input amplitudes 2 s and 2 s + 1), and a wave takes 16 tile columns per
+// instruction sequence.  Operand layouts (checked on the device): A[i][k] in
+// lane i + 16 k, B[k][j] in lane j + 16 k, D[i][j] in lane j + 16 (i % 4),
+// element i / 4, so a lane holds one component of four output amplitudes.
+template <int K, int MB>
+__device__ __forceinline__ void block_mfma_f64(cplx<double> *lds, const LTOp &op,
+                                               const double *__restrict__ F) {
+    constexpr int D = 1 << K;
+    constexpr int NMB = D / 8;                        // M blocks of 16 real rows
+    constexpr int NS = D / 2;                         // steps of 4 real columns
+    constexpr int NGRP = ((1 << MB) >> K) / 16;       // groups of 16 tile columns
+    static_assert(NGRP >= 1, "the tile needs 16 columns per block");
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15;
+    const int kq = lane >> 4;                         // B row within a step
+    int pos[K];
+#pragma unroll
+    for (int j = 0; j < K; j++) pos[j] = op.pos[j];
+    uint32_t off[D];
+    off[0] = 0;
+#pragma unroll
+    for (int s = 1; s < D; s++) off[s] = off[s & (s - 1)] | (1u << pos[__builtin_ctz(s)]);
+    for (int grp = wave; grp < NGRP; grp += BLOCK / 64) {
+        uint32_t base = (uint32_t)(grp * 16 + col);
+#pragma unroll
+        for (int j = 0; j < K; j++) base = insert_zero32(base, pos[j]);
+        // B operands: component kq & 1 of input amplitude 2 s + (kq >> 1)
+        double bv[NS];
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            const cplx<double> v = lds[base + off[2 * s + (kq >> 1)]];
+            bv[s] = (kq & 1) ? v.im : v.re;
+        }
+        // every input of the column group is in registers now, so each M
+        // block is stored as soon as it is done (its A operands are loaded
+        // per block: the rolled loop keeps one block's fragments live)
+#pragma unroll 1
+        for (int mb = 0; mb < NMB; mb++) {
+            doublex4 acc;
+#pragma unroll
+            for (int e = 0; e < 4; e++) acc[e] = 0.0;
+            const double *Fm = F + mb * NS * 64 + lane;
+#pragma unroll
+            for (int s = 0; s < NS; s++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Fm[s * 64], bv[s], acc, 0, 0, 0);
+            // element e = row 16 mb + 4 e + kq of column col: component
+            // kq & 1 of output amplitude 8 mb + 2 e + (kq >> 1)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int a = 8 * mb + 2 * e + (kq >> 1);   // lane-dependent
+                uint32_t oa = 0;
+#pragma unroll
+                for (int j = 0; j < K; j++)
+                    if ((a >> j) & 1) oa |= 1u << pos[j];
+                double *dst = reinterpret_cast<double *>(lds + base + oa) + (kq & 1);
+                *dst = acc[e];
+            }
+        }
+    }
+}
+
+template <typename T, int MB, int KMAX, bool VALU_WIDE>
 __device__ __forceinline__ void run_block(cplx<T> *lds, const LTOp &op, const uint8_t *hdr) {
     const cplx<T> *U = reinterpret_cast<const cplx<T> *>(hdr + op.mat_off);
     const float *F = reinterpret_cast<const float *>(hdr + op.mat_off);
+    const double *Fd = reinterpret_cast<const double *>(hdr + op.mat_off);
+    // op.mfma: the plan chose the matrix cores for this block and stored its
+    // operand fragments; it does so for k = 4, 5 in complex64 and k = 5 in
+    // complex128, where the tile has the columns the fragments need
+    // (2^(MB - k) >= 32 in complex64, >= 64 in complex128)
     switch (op.k) {
     case 1: block_valu<T, 1, MB>(lds, op, U); break;
     case 2: block_valu<T, 2, MB>(lds, op, U); break;
     case 3: block_valu<T, 3, MB>(lds, op, U); break;
-    case 4:   // op.mfma: the plan chose the matrix cores for this block
+    case 4:
         if constexpr (KMAX >= 4) {
             if constexpr (sizeof(T) == 4 && MB >= 9) {
                 if (op.mfma) { block_mfma<4, MB>(lds, op, F); break; }
             }
-            block_valu<T, 4, MB>(lds, op, U);
+            if constexpr (VALU_WIDE) block_valu<T, 4, MB>(lds, op, U);
         }
         break;
     default:
@@ -258,7 +331,10 @@ __device__ __forceinline__ void run_block(cplx<T> *lds, const LTOp &op, const ui
             if constexpr (sizeof(T) == 4 && MB >= 10) {
                 if (op.mfma) { block_mfma<5, MB>(lds, op, F); break; }
             }
-            block_valu<T, 5, MB>(lds, op, U);
+            if constexpr (sizeof(T) == 8 && MB >= 11) {
+                if (op.mfma) { block_mfma_f64<5, MB>((cplx<double> *)lds, op, Fd); break; }
+            }
+            if constexpr (VALU_WIDE) block_valu<T, 5, MB>(lds, op, U);
         }
         break;
     }
@@ -296,7 +372,7 @@ __device__ __forceinline__ void diag_regs(cplx<T> (&v)[PER], const LTOp &op, con
     }
 }
 
-template <typename T, int MB, int KMAX>
+template <typename T, int MB, int KMAX, bool VALU_WIDE>
 __global__ __launch_bounds__(BLOCK) void k_ldstile(cplx<T> *__restrict__ psi,
                                                    const uint8_t *__restrict__ prog,
                                                    uint64_t ntiles) {
@@ -347,7 +423,7 @@ __global__ __launch_bounds__(BLOCK) void k_ldstile(cplx<T> *__restrict__ psi,
         for (int o = first; o <= last; o++) {
             const LTOp &op = ops[o];
             if (op.kind == LT_BLOCK) {
-                run_block<T, MB, KMAX>(lds, op, prog);
+                run_block<T, MB, KMAX, VALU_WIDE>(lds, op, prog);
             } else {
 #pragma unroll
                 for (int i = 0; i < PER; i++) v[i] = lds[t + BLOCK * i];
@@ -431,25 +507,32 @@ static sv_status launch_typed(sv_state *st, const Plan &plan, const Op &op, cplx
         const uint64_t ntiles = N >> op.vbits;
         const unsigned grid = (unsigned)ntiles;
         // kernel variant by tile width and widest block (k <= 3 variants
-        // carry fewer registers)
+        // carry fewer registers, and so do wide variants whose blocks of 4
+        // and 5 qubits all run on the matrix cores: op.q0 = 1)
         const bool wide = op.q1 > 3;
-#define LT_CASE(MB)                                                                                       \
-    case MB:                                                                                              \
-        if (wide) hipLaunchKernelGGL((k_ldstile<T, MB, 5>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles); \
-        else hipLaunchKernelGGL((k_ldstile<T, MB, 3>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles);      \
+        const bool mfma_only = wide && op.q0 == 1;
+#define LT_LAUNCH(MB, KM, VW) \
+    hipLaunchKernelGGL((k_ldstile<T, MB, KM, VW>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles)
+#define LT_CASE(MB)                                   \
+    case MB:                                          \
+        if (mfma_only) LT_LAUNCH(MB, 5, false);       \
+        else if (wide) LT_LAUNCH(MB, 5, true);        \
+        else LT_LAUNCH(MB, 3, false);                 \
         break;
         switch (op.vbits) {
             LT_CASE(8) LT_CASE(9) LT_CASE(10) LT_CASE(11) LT_CASE(12)
         case 13:
             if constexpr (sizeof(T) == 4) {
-                if (wide) hipLaunchKernelGGL((k_ldstile<T, 13, 5>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles);
-                else hipLaunchKernelGGL((k_ldstile<T, 13, 3>), dim3(grid), dim3(BLOCK), 0, s, psi, prog, ntiles);
+                if (mfma_only) LT_LAUNCH(13, 5, false);
+                else if (wide) LT_LAUNCH(13, 5, true);
+                else LT_LAUNCH(13, 3, false);
                 break;
             }
             return fail(SV_EINVAL, "LDS tile too large for complex128");
         default: return fail(SV_EINVAL, "LDS tile width out of range");
         }
 #undef LT_CASE
+#undef LT_LAUNCH
         break;
     }
     default:

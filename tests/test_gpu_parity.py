@@ -24,7 +24,10 @@ from paper_1608_00263_amd import sv  # noqa: E402  (fails loudly if libsv.so is 
 TOL = {"c64": 1e-4, "c128": 1e-11}
 MODES = [("plain", 0, 0), ("spec", 0, 0), ("regtile", 0, 0), ("regtile", 0, 3), ("regtile", 0, 6),
          ("fused", 2, 0), ("fused", 3, 0), ("fused", 4, 0), ("fused", 5, 0), ("tiled", 3, 10),
-         ("tiled", 4, 12), ("tiled", 5, 13)]
+         ("tiled", 4, 12), ("tiled", 5, 13),
+         # tiles just wide enough for the matrix-core fragments (complex64
+         # from 2^(m-k) = 32 columns, complex128 from 64) and just below
+         ("tiled", 4, 9), ("tiled", 4, 10), ("tiled", 5, 11)]
 
 
 def run_gpu(circ, dtype, mode, k, t, psi0=None):

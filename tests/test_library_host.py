@@ -44,7 +44,10 @@ def test_library_exports_every_declared_symbol():
 
 MODES = [("plain", 0, 0), ("spec", 0, 0), ("regtile", 0, 0), ("regtile", 0, 2), ("regtile", 0, 6),
          ("fused", 1, 0), ("fused", 2, 0), ("fused", 3, 0), ("fused", 4, 0), ("fused", 5, 0),
-         ("tiled", 2, 9), ("tiled", 3, 11), ("tiled", 4, 12), ("tiled", 5, 13)]
+         ("tiled", 2, 9), ("tiled", 3, 11), ("tiled", 4, 12), ("tiled", 5, 13),
+         # narrow tiles: the matrix cores only where a tile has the columns
+         # their fragments need (vector ALU otherwise)
+         ("tiled", 4, 8), ("tiled", 4, 9), ("tiled", 5, 10)]
 
 
 @pytest.mark.parametrize("mode,k,t", MODES)
