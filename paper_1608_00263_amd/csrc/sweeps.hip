@@ -397,24 +397,27 @@ __global__ __launch_bounds__(BLOCK) void k_ldstile(cplx<T> *__restrict__ psi,
         if (ops[o].kind == LT_BLOCK) { if (first == nops) first = o; last = o; }
 
     // element i of this thread: local index j = t + 256 i; lane bits = t & 63,
-    // row = j >> 6 = (t >> 6) + 4 i (wave-uniform)
+    // row = j >> 6 = (t >> 6) + 4 i (wave-uniform).  The row's global offset
+    // is the sum of 2^hq[b] over its set bits: the wave's part once, the part
+    // of i from compile-time bit patterns, both in scalar registers, and the
+    // row pointer is wave-uniform (scalar base + lane offset addressing)
     const int t = threadIdx.x;
     const int col = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-    uint64_t rowoff[PER];
+    uint64_t woff = 0;
 #pragma unroll
-    for (int i = 0; i < PER; i++) {
-        const uint32_t row = (uint32_t)(wave + 4 * i);
-        uint64_t o = 0;
+    for (int b = 0; b < 2 && b < NH; b++)
+        if ((wave >> b) & 1) woff |= 1ull << hq[b];
+    auto row_ptr = [&](int i) {
+        uint64_t o = woff;
 #pragma unroll
-        for (int b = 0; b < NH; b++)
-            if ((row >> b) & 1) o |= 1ull << hq[b];
-        rowoff[i] = o;
-    }
+        for (int b = 2; b < NH; b++)
+            if (((4 * i) >> b) & 1) o |= 1ull << hq[b];
+        return uniform_ptr(psi + (base + o));
+    };
     cplx<T> v[PER];
-    const cplx<T> *src = psi + base + col;
 #pragma unroll
-    for (int i = 0; i < PER; i++) v[i] = src[rowoff[i]];
+    for (int i = 0; i < PER; i++) v[i] = row_ptr(i)[col];
     for (int o = 0; o < first && o < nops; o++) diag_regs<T, PER>(v, ops[o], terms, base);
     if (first < nops) {
 #pragma unroll
@@ -438,9 +441,8 @@ __global__ __launch_bounds__(BLOCK) void k_ldstile(cplx<T> *__restrict__ psi,
     }
     for (int o = (first < nops ? last + 1 : nops); o < nops; o++)
         diag_regs<T, PER>(v, ops[o], terms, base);
-    cplx<T> *dst = psi + base + col;
 #pragma unroll
-    for (int i = 0; i < PER; i++) dst[rowoff[i]] = v[i];
+    for (int i = 0; i < PER; i++) row_ptr(i)[col] = v[i];
 }
 
 // ---------------------------------------------------------------------------
