@@ -40,9 +40,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3   # dense FP32 matrix peak of the MI355X
+PEAK_FP64_MFMA_TFLOPS = 78.6    # dense FP64 matrix peak of the MI355X
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_regtile_c2_traffic.txt")
-# sources of the register-tile sweep and its programs: the counter-based
-# traffic of the profile summary is reported only while these are unchanged
+TRAFFIC_FILE_C128 = os.path.join(ROOT, "profiles", "k_regtile_c2_c128_traffic.txt")
+MFMA_FILE = os.path.join(ROOT, "profiles", "k_ldstile_c2_mfma.txt")
+# sources of the sweep kernels and their programs: the counter figures of the
+# profile summaries are reported only while these are unchanged
 KERNEL_SOURCES = ["paper_1608_00263_amd/csrc/device_common.h", "paper_1608_00263_amd/csrc/sweeps.hip",
                   "paper_1608_00263_amd/csrc/internal.h", "paper_1608_00263_amd/csrc/plan.cpp"]
 
@@ -56,35 +59,58 @@ def kernel_sha1():
     return h.hexdigest()
 
 
-def profile_summary(tile):
-    """Key-value lines of the committed counter summary of the register-tile
-    sweep, or {} when it is missing, for another tile width, or older than
-    the kernel sources."""
+def read_summary(path):
+    """Key-value lines of a committed counter summary, or {} when it is
+    missing or older than the kernel sources."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             for line in fh:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
-        if kv.get("source_sha1") != kernel_sha1() or int(kv.get("register_qubits", -1)) != tile:
-            return {}
-        return kv
-    except (OSError, ValueError):
+        return kv if kv.get("source_sha1") == kernel_sha1() else {}
+    except OSError:
         return {}
 
 
-def measured_traffic(tile):
+def profile_summary(tile, path=TRAFFIC_FILE):
+    """The register-tile counter summary for this tile width, or {}."""
+    kv = read_summary(path)
+    try:
+        return kv if int(kv.get("register_qubits", -1)) == tile else {}
+    except ValueError:
+        return {}
+
+
+def measured_traffic(tile, path=TRAFFIC_FILE):
     """HBM bytes per register-tile launch from the counter summary, or None."""
-    v = profile_summary(tile).get("traffic_bytes_per_launch")
+    v = profile_summary(tile, path).get("traffic_bytes_per_launch")
     return float(v) if v is not None else None
 
 
-def measured_valu_frac(tile):
+def measured_valu_frac(tile, path=TRAFFIC_FILE):
     """Vector-ALU issue share of the register-tile sweeps from the counter
     summary (instructions over one per CU-cycle at 2.4 GHz), or None."""
-    v = profile_summary(tile).get("valu_frac")
+    v = profile_summary(tile, path).get("valu_frac")
     return float(v) if v is not None else None
+
+
+def measured_mfma():
+    """Matrix-core counters of the LDS-tile modes from their summary: per
+    mode, the busy share of the matrix cores and the rate of their flops
+    while the mode's sweeps run; {} when missing or stale."""
+    kv = read_summary(MFMA_FILE)
+    out = {}
+    for k, v in kv.items():
+        if k.startswith("mode "):
+            f = v.split()
+            try:
+                out[k[5:]] = {"mfma_util": float(f[0]), "mfma_TFLOPs": float(f[1]), "frac_of_peak": float(f[2]),
+                              "peak_TFLOPs": float(f[3])}
+            except (IndexError, ValueError):
+                pass
+    return out
 
 
 def log(msg):
@@ -109,6 +135,7 @@ def parse():
     ap.add_argument("--no-dense", action="store_true", help="skip the denser periodic family")
     ap.add_argument("--no-noise", action="store_true", help="skip the noisy trajectories and single errors")
     ap.add_argument("--no-c128-roofline", action="store_true", help="skip the complex128 sweep roofline")
+    ap.add_argument("--modes", default="", help="comma-separated circuit_s keys to time (default: all)")
     ap.add_argument("--ensemble", type=int, default=512, help="ensemble instances")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, copy an 8 GiB buffer three times (a plain copy "
@@ -285,7 +312,11 @@ def main():
     if not a.no_c128_roofline:
         out["roofline_c128"] = roofline_c128(sv, C, circ, torch)
     if not a.no_modes:
-        out["circuit_s"] = mode_timings(sv, C, circ, torch)
+        only = set(x for x in a.modes.split(",") if x)
+        out["circuit_s"] = mode_timings(sv, C, circ, torch, only)
+        mf = measured_mfma()
+        if mf:
+            out["mfma"] = mf
     if not a.no_grad:
         out["grad"] = grad_timings(sv, C, torch)
     if not a.no_cycles:
@@ -360,7 +391,8 @@ def roofline_c128(sv, C, circ, torch, reps=5):
     torch.cuda.empty_cache()
     log("c128 register tiles: %.2f ms, %d sweeps, %.0f GB/s" % (tot, nl, achieved))
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBPS, 4), "kernel": "k_regtile<double,5>",
+            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(5, TRAFFIC_FILE_C128),
+            "valu_frac": measured_valu_frac(5, TRAFFIC_FILE_C128), "kernel": "k_regtile<double,5>",
             "launches": nl, "launch_avg_ms": round(dom_ms / nl, 4), "bytes_per_launch": round(dom_by / nl, 1),
             "circuit_ms": round(tot, 3), "workload": "5x6 grid, 30 qubits, depth 40, complex128 (16 GiB)"}
 
@@ -375,11 +407,11 @@ def _median_time(fn, reps):
     return statistics.median(ts)
 
 
-def mode_timings(sv, C, circ, torch):
+def mode_timings(sv, C, circ, torch, only=()):
     """Seconds of the 30-qubit circuit per planning mode (median of 5 runs,
     3 for modes slower than one second), and every mode's distance from the
     complex128 per-gate state (which the test suite checks against the FP64
-    reference at 1e-11)."""
+    reference at 1e-11).  only: the keys to time (all when empty)."""
     res = {}
     ref = sv.State(circ.n, "c128")
     ref.apply(circ, "plain", from_zero=True)
@@ -402,6 +434,10 @@ def mode_timings(sv, C, circ, torch):
         for mode, k, t, nomf in modes:
             budget = 60 if mode.endswith("_b60") else 0
             mode = mode.replace("_b60", "")
+            key = "%s_%s%s%s%s" % (dtype, mode, ("_k%d" % k if k else "") + ("_t%d" % t if t else ""),
+                                   "_valu" if nomf else "", "_b%d" % budget if budget else "")
+            if only and key not in only:
+                continue
             st.apply(circ, mode, k, t, args=args, from_zero=True, no_mfma=nomf, budget=budget)   # plan + warm / tune
             if mode == "auto":
                 for _ in range(8):
@@ -415,8 +451,6 @@ def mode_timings(sv, C, circ, torch):
             dt = _median_time(run, 3 if t_one > 1.0 else 5)
             sw, by = st.plan_info(circ, mode, k, t, no_mfma=nomf, from_zero=True, budget=budget)
             d = float(torch.linalg.vector_norm(st.tensor.to(torch.complex128) - ref.tensor))
-            key = "%s_%s%s%s%s" % (dtype, mode, ("_k%d" % k if k else "") + ("_t%d" % t if t else ""),
-                                   "_valu" if nomf else "", "_b%d" % budget if budget else "")
             res[key] = {"s": round(dt, 4), "sweeps": sw, "GBps": round(by / dt / 1e9, 1),
                         "frac_of_peak": round(by / dt / 1e9 / PEAK_HBM_GBPS, 4), "err_vs_c128": float("%.3g" % d)}
             if mode in ("fused", "tiled"):
@@ -426,7 +460,8 @@ def mode_timings(sv, C, circ, torch):
                     # MFMA block flops over the whole circuit time: a lower
                     # bound on the rate of the matrix cores while they run
                     res[key]["mfma_TFLOPs"] = round(mf / dt / 1e12, 2)
-                    res[key]["mfma_frac_of_peak"] = round(mf / dt / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4)
+                    peak = PEAK_FP32_MFMA_TFLOPS if dtype == "c64" else PEAK_FP64_MFMA_TFLOPS
+                    res[key]["mfma_frac_of_peak"] = round(mf / dt / 1e12 / peak, 4)
             if mode == "auto":
                 res[key]["choice"] = st.autotune(circ, from_zero=True)[:3]
             log("%s: %.3f s, %d sweeps, |d| %.2e" % (key, dt, sw, d))
@@ -442,7 +477,8 @@ def mode_timings(sv, C, circ, torch):
 def dense_block_flops(sv, circ, dtype, mode, k, t, nomf):
     """Algorithmic flops of the plan's dense 2^k blocks (8 * 2^k per
     amplitude each: a complex 2^k x 2^k matrix on every 2^k-vector), and of
-    those that run on MFMA, read from the host description of the plan."""
+    those that run on MFMA (k = 4, 5 in complex64, k = 5 in complex128), read
+    from the host description of the plan."""
     import re
     d = sv.host_plan_describe(circ, dtype, mode, k, t, from_zero=True, no_mfma=nomf)
     N = float(2 ** circ.n)
@@ -452,7 +488,7 @@ def dense_block_flops(sv, circ, dtype, mode, k, t, nomf):
             kk = int(ch)
             f = 8.0 * 2 ** kk * N
             tot += f
-            if m == "1" and kk >= 4:
+            if m == "1" and kk >= (4 if dtype == "c64" else 5):
                 mf += f
     return tot, mf
 
