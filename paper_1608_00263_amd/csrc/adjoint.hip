@@ -251,9 +251,12 @@ __device__ __forceinline__ double lane_rot_dispatch(cplx<T> (&phi)[NR], cplx<T> 
 }
 
 // phi is read from phi_src (the state, or the checkpoint of the state after
-// the forward sweep this one reverses) and written to phi_g.
+// the forward sweep this one reverses) and written to phi_g.  Two tiles (phi
+// and mu) of 2^VB amplitudes per lane: in complex64 up to 5 register qubits
+// the kernel fits 3 waves per SIMD (168 registers in all), which the launch
+// bound keeps (two registers more left 2 waves: 24% slower, measured).
 template <typename T, int VB>
-__global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi_g, const cplx<T> *__restrict__ phi_src,
+__global__ __launch_bounds__(BLOCK, (sizeof(T) == 4 && VB <= 5) ? 3 : 1) void k_regtile_adj(cplx<T> *__restrict__ phi_g, const cplx<T> *__restrict__ phi_src,
                                                        cplx<T> *__restrict__ mu_g,
                                                        const uint8_t *__restrict__ prog, uint64_t ntiles,
                                                        double *__restrict__ gpart, int nslots) {
@@ -326,8 +329,8 @@ __global__ __launch_bounds__(BLOCK) void k_regtile_adj(cplx<T> *__restrict__ phi
                 reg_gate_dispatch<T, NR>(phi, u, arg, form);
                 reg_gate_dispatch<T, NR>(mu, u, arg, form);
             } else {
-                lane_gate_dispatch<T, NR>(phi, u, arg, lane, form);
-                lane_gate_dispatch<T, NR>(mu, u, arg, lane, form);
+                lane_gate_dispatch<T, NR, false>(phi, u, arg, lane, form);
+                lane_gate_dispatch<T, NR, false>(mu, u, arg, lane, form);
             }
         } else if (kind == RT_SIGNS) {
             uint64_t par = 0;

@@ -47,33 +47,40 @@ constexpr int BLOCK = 256;
 // lanes).  Bits 0, 1 and 3 take one DPP lane move within rows of 16 (quad
 // permutations, rotation of the row by 8), bit 2 two (half-row mirror, then
 // quad reverse), bit 4 a ds_swizzle in xor mode (and mask 0x1f, xor mask
-// 16), bit 5 a ds_bpermute.  The last move of bits 0..3 is written as an
+// 16), bit 5 a ds_bpermute.  FOLD writes the last move of bits 0..3 as an
 // update with bound_ctrl and a zero old value: every source lane is inside
 // the row and active, so it equals a plain move, and in that form the
-// compiler merges it into a following add or subtract (one instruction).
-template <int B>
+// compiler merges it into a following add, subtract or multiply (one
+// instruction); before other consumers (fused multiply-adds) it would only
+// hold a register, so they take the plain move.
+template <int CTRL, bool FOLD>
+__device__ __forceinline__ int dpp_move(int x) {
+    if constexpr (FOLD) return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, true);
+    else return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, false);
+}
+template <int B, bool FOLD = false>
 __device__ __forceinline__ int lane_xor_i(int v) {
-    if constexpr (B == 0) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);   // quad_perm 1,0,3,2
-    if constexpr (B == 1) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);   // quad_perm 2,3,0,1
+    if constexpr (B == 0) return dpp_move<0xB1, FOLD>(v);   // quad_perm 1,0,3,2
+    if constexpr (B == 1) return dpp_move<0x4E, FOLD>(v);   // quad_perm 2,3,0,1
     if constexpr (B == 2) {   // i ^ 7 (half-row mirror), then i ^ 3 (quad reverse): i ^ 4
         int m = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);
-        return __builtin_amdgcn_update_dpp(0, m, 0x1B, 0xF, 0xF, true);
+        return dpp_move<0x1B, FOLD>(m);
     }
-    if constexpr (B == 3) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, true);   // row_ror 8: i ^ 8
+    if constexpr (B == 3) return dpp_move<0x128, FOLD>(v);   // row_ror 8: i ^ 8
     if constexpr (B == 4) return __builtin_amdgcn_ds_swizzle(v, 0x401F);   // lane ^ 16
     if constexpr (B == 5) return __shfl_xor(v, 32, 64);
     return v;
 }
 
-template <int B>
+template <int B, bool FOLD = false>
 __device__ __forceinline__ float lane_xor(float v) {
-    return __int_as_float(lane_xor_i<B>(__float_as_int(v)));
+    return __int_as_float(lane_xor_i<B, FOLD>(__float_as_int(v)));
 }
-template <int B>
+template <int B, bool FOLD = false>
 __device__ __forceinline__ double lane_xor(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = lane_xor_i<B>((int)(b & 0xffffffffll));
-    const int hi = lane_xor_i<B>((int)(b >> 32));
+    const int lo = lane_xor_i<B, FOLD>((int)(b & 0xffffffffll));
+    const int hi = lane_xor_i<B, FOLD>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ float lane_xor(float v, int m) { return __shfl_xor(v, m, 64); }
@@ -206,7 +213,10 @@ __device__ __forceinline__ void half_swap(double &x, double &y) {
 // (self) and its partner's (p); hi = the lane's bit B.  Bits 4 and 5 swap
 // register halves instead so that each lane applies the gate to a whole
 // pair (no lane-dependent coefficients).
-template <typename T, int NR, int B, int FORM>
+// FOLDOK: the cross-lane moves may be merged into their consumers (see
+// lane_xor_i); kernels that keep two tiles in registers pass false, since the
+// merged in-place update needs one more register per amplitude in flight.
+template <typename T, int NR, int B, int FORM, bool FOLDOK = true>
 __device__ __forceinline__ void lane_gate_f(cplx<T> (&a)[NR], const Mat2<T> &u, int lane) {
     if constexpr (B >= 4 && FORM != F_PHASE && NR >= 2) {
 #pragma unroll
@@ -256,11 +266,14 @@ __device__ __forceinline__ void lane_gate_f(cplx<T> (&a)[NR], const Mat2<T> &u, 
     } else if constexpr (FORM == F_SYDG) {
         sg = hi ? (T)-1 : (T)1;     // lo: self + p, hi: self - p
     }
+    // forms whose partner terms feed an add, subtract or multiply
+    constexpr bool FOLD =
+        FOLDOK && (FORM == F_SX || FORM == F_SXDG || FORM == F_RX || FORM == F_RY || FORM == F_REAL);
 #pragma unroll
     for (int r = 0; r < NR; r++) {
         cplx<T> p;
-        p.re = lane_xor<B>(a[r].re);
-        p.im = lane_xor<B>(a[r].im);
+        p.re = lane_xor<B, FOLD>(a[r].re);
+        p.im = lane_xor<B, FOLD>(a[r].im);
         cplx<T> s = a[r], o;
         if constexpr (FORM == F_GEN) {
             o = cmad(cp, p, cmul(cs, s));
@@ -285,34 +298,34 @@ __device__ __forceinline__ void lane_gate_f(cplx<T> (&a)[NR], const Mat2<T> &u, 
     }
 }
 
-template <typename T, int NR, int B>
+template <typename T, int NR, int B, bool FOLDOK = true>
 __device__ __forceinline__ void lane_gate_b(cplx<T> (&a)[NR], const Mat2<T> &u, int lane, int form) {
     switch (form) {
-    case F_H: lane_gate_f<T, NR, B, F_H>(a, u, lane); break;
-    case F_SX: lane_gate_f<T, NR, B, F_SX>(a, u, lane); break;
-    case F_SY: lane_gate_f<T, NR, B, F_SY>(a, u, lane); break;
-    case F_SXDG: lane_gate_f<T, NR, B, F_SXDG>(a, u, lane); break;
-    case F_SYDG: lane_gate_f<T, NR, B, F_SYDG>(a, u, lane); break;
-    case F_PHASE: lane_gate_f<T, NR, B, F_PHASE>(a, u, lane); break;
-    case F_RX: lane_gate_f<T, NR, B, F_RX>(a, u, lane); break;
-    case F_RY: lane_gate_f<T, NR, B, F_RY>(a, u, lane); break;
-    case F_REAL: lane_gate_f<T, NR, B, F_REAL>(a, u, lane); break;
-    case F_TRX: lane_gate_f<T, NR, B, F_TRX>(a, u, lane); break;
-    case F_TRY: lane_gate_f<T, NR, B, F_TRY>(a, u, lane); break;
-    default: lane_gate_f<T, NR, B, F_GEN>(a, u, lane); break;
+    case F_H: lane_gate_f<T, NR, B, F_H, FOLDOK>(a, u, lane); break;
+    case F_SX: lane_gate_f<T, NR, B, F_SX, FOLDOK>(a, u, lane); break;
+    case F_SY: lane_gate_f<T, NR, B, F_SY, FOLDOK>(a, u, lane); break;
+    case F_SXDG: lane_gate_f<T, NR, B, F_SXDG, FOLDOK>(a, u, lane); break;
+    case F_SYDG: lane_gate_f<T, NR, B, F_SYDG, FOLDOK>(a, u, lane); break;
+    case F_PHASE: lane_gate_f<T, NR, B, F_PHASE, FOLDOK>(a, u, lane); break;
+    case F_RX: lane_gate_f<T, NR, B, F_RX, FOLDOK>(a, u, lane); break;
+    case F_RY: lane_gate_f<T, NR, B, F_RY, FOLDOK>(a, u, lane); break;
+    case F_REAL: lane_gate_f<T, NR, B, F_REAL, FOLDOK>(a, u, lane); break;
+    case F_TRX: lane_gate_f<T, NR, B, F_TRX, FOLDOK>(a, u, lane); break;
+    case F_TRY: lane_gate_f<T, NR, B, F_TRY, FOLDOK>(a, u, lane); break;
+    default: lane_gate_f<T, NR, B, F_GEN, FOLDOK>(a, u, lane); break;
     }
 }
 
-template <typename T, int NR>
+template <typename T, int NR, bool FOLDOK = true>
 __device__ __forceinline__ void lane_gate_dispatch(cplx<T> (&a)[NR], const Mat2<T> &u, int b, int lane,
                                                    int form = F_GEN) {
     switch (b) {
-    case 0: lane_gate_b<T, NR, 0>(a, u, lane, form); break;
-    case 1: lane_gate_b<T, NR, 1>(a, u, lane, form); break;
-    case 2: lane_gate_b<T, NR, 2>(a, u, lane, form); break;
-    case 3: lane_gate_b<T, NR, 3>(a, u, lane, form); break;
-    case 4: lane_gate_b<T, NR, 4>(a, u, lane, form); break;
-    default: lane_gate_b<T, NR, 5>(a, u, lane, form); break;
+    case 0: lane_gate_b<T, NR, 0, FOLDOK>(a, u, lane, form); break;
+    case 1: lane_gate_b<T, NR, 1, FOLDOK>(a, u, lane, form); break;
+    case 2: lane_gate_b<T, NR, 2, FOLDOK>(a, u, lane, form); break;
+    case 3: lane_gate_b<T, NR, 3, FOLDOK>(a, u, lane, form); break;
+    case 4: lane_gate_b<T, NR, 4, FOLDOK>(a, u, lane, form); break;
+    default: lane_gate_b<T, NR, 5, FOLDOK>(a, u, lane, form); break;
     }
 }
 

@@ -114,8 +114,10 @@ __global__ __launch_bounds__(BLOCK) void k_cz(cplx<T> *__restrict__ psi, int a, 
 // ---------------------------------------------------------------------------
 // register tiles
 // ---------------------------------------------------------------------------
+// Up to 128 registers of tile data (2^VB amplitudes per lane) the kernel fits
+// 3 waves per SIMD, which the launch bound keeps.
 template <typename T, int VB>
-__global__ __launch_bounds__(BLOCK) void k_regtile(cplx<T> *__restrict__ psi,
+__global__ __launch_bounds__(BLOCK, (sizeof(T) << VB) <= 256 ? 3 : 1) void k_regtile(cplx<T> *__restrict__ psi,
                                                    const uint8_t *__restrict__ prog,
                                                    uint64_t ntiles, cplx<T> *__restrict__ ck) {
     const int lane = threadIdx.x & 63;
@@ -417,7 +419,11 @@ __global__ __launch_bounds__(BLOCK) void k_ldstile(cplx<T> *__restrict__ psi,
     };
     cplx<T> v[PER];
 #pragma unroll
-    for (int i = 0; i < PER; i++) v[i] = row_ptr(i)[col];
+    for (int i = 0; i < PER; i++) {
+        const auto p = row_ptr(i) + col;
+        v[i].re = p->re;
+        v[i].im = p->im;
+    }
     for (int o = 0; o < first && o < nops; o++) diag_regs<T, PER>(v, ops[o], terms, base);
     if (first < nops) {
 #pragma unroll
@@ -442,7 +448,11 @@ __global__ __launch_bounds__(BLOCK) void k_ldstile(cplx<T> *__restrict__ psi,
     for (int o = (first < nops ? last + 1 : nops); o < nops; o++)
         diag_regs<T, PER>(v, ops[o], terms, base);
 #pragma unroll
-    for (int i = 0; i < PER; i++) row_ptr(i)[col] = v[i];
+    for (int i = 0; i < PER; i++) {
+        const auto p = row_ptr(i) + col;
+        p->re = v[i].re;
+        p->im = v[i].im;
+    }
 }
 
 // ---------------------------------------------------------------------------
