@@ -233,6 +233,9 @@ def test_c4_adjoint_full_size():
     st.close()
     s128 = sv.State(25, "c128")
     loss128, g128 = s128.backward(circ, xs)
+    print("C4 gradients: |g| = %.4e, max |g64 - g128| = %.3e, |g64 - g128| / |g128| = %.3e, loss diff %.2e"
+          % (np.linalg.norm(g128), np.abs(g64 - g128).max(), np.linalg.norm(g64 - g128) / np.linalg.norm(g128),
+             abs(loss64 - loss128)), flush=True)
     assert abs(loss64 - loss128) < 1e-4
     assert np.abs(g64 - g128).max() < 1e-4
     assert np.linalg.norm(g64 - g128) <= 1e-3 * np.linalg.norm(g128)
