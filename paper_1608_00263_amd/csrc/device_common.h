@@ -473,10 +473,46 @@ __device__ __forceinline__ void regtile_apply(cplx<T> *__restrict__ psi, const u
         // the Hadamard layer on |0..0>: every amplitude is 2^{-n/2}
         double vd = ldexp(1.0, -(gen_n / 2));
         if (gen_n & 1) vd *= 0.70710678118654752440;
-        const T v = (T)(vd * scale);
+        vd *= scale;
         scale = 1.0;
+        if (h->gph_off > 0) {
+            // diagonals folded in: amplitude = v c prod over the set bits of
+            // its index of the ratio of that qubit (outside qubits from the
+            // tile base, lane bits per lane, register slots by doubling)
+            const cptr<RTGenPhases> gp = (cptr<RTGenPhases>)(prog + h->gph_off);
+            const cptr<RTGenOut> go = (cptr<RTGenOut>)(prog + h->gph_off + sizeof(RTGenPhases));
+            double cr = vd * gp->c[0], ci = vd * gp->c[1];
+            const int nout = h->gph_nout;
+            for (int k = 0; k < nout; k++) {
+                if ((base & go[k].mask) == 0) continue;
+                const double xr = go[k].r[0], xi = go[k].r[1];
+                const double t = cr * xr - ci * xi;
+                ci = cr * xi + ci * xr;
+                cr = t;
+            }
 #pragma unroll
-        for (int r = 0; r < NR; r++) { a[r].re = v; a[r].im = (T)0; }
+            for (int b = 0; b < 6; b++) {
+                const bool on = (lane >> b) & 1;
+                const double xr = on ? gp->lane[b][0] : 1.0, xi = on ? gp->lane[b][1] : 0.0;
+                const double t = cr * xr - ci * xi;
+                ci = cr * xi + ci * xr;
+                cr = t;
+            }
+            a[0].re = (T)cr;
+            a[0].im = (T)ci;
+#pragma unroll
+            for (int sb = 0; sb < VB; sb++) {
+                cplx<T> f;
+                f.re = (T)gp->reg[sb][0];
+                f.im = (T)gp->reg[sb][1];
+#pragma unroll
+                for (int r = 1 << sb; r < (2 << sb); r++) a[r] = cmul(a[r - (1 << sb)], f);
+            }
+        } else {
+            const T v = (T)vd;
+#pragma unroll
+            for (int r = 0; r < NR; r++) { a[r].re = v; a[r].im = (T)0; }
+        }
     } else if (rows) {
 #pragma unroll
         for (int r = 0; r < NR; r++) a[r] = gload<T>(uniform_ptr(psi + (base + reg_offset<VB>(bq, r))) + lane);

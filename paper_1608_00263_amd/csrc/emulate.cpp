@@ -39,12 +39,31 @@ static void emulate_regtile(const Plan &plan, const Op &op, int n, cx *psi) {
     for (uint64_t tile = 0; tile < ntiles; tile++) {
         uint64_t base = tile << 4;
         for (int i = 0; i < vb + 2; i++) base = ins0(base, h->tq[i]);
+        // generated state: 2^{-n/2} times the folded diagonal phases (the
+        // product of c and the ratios of the qubits whose bit is set)
+        cx gtile = 1.0;
+        const RTGenPhases *gp = nullptr;
+        if (h->gen_n > 0 && h->gph_off > 0) {
+            gp = (const RTGenPhases *)((const uint8_t *)h + h->gph_off);
+            const RTGenOut *go = (const RTGenOut *)((const uint8_t *)gp + sizeof(RTGenPhases));
+            gtile = cx(gp->c[0], gp->c[1]);
+            for (int k = 0; k < h->gph_nout; k++)
+                if (base & go[k].mask) gtile *= cx(go[k].r[0], go[k].r[1]);
+        }
         for (int l = 0; l < 64; l++)
             for (int r = 0; r < nr; r++) {
                 if (h->gen_n > 0) {
                     double v = std::ldexp(1.0, -(h->gen_n / 2));
                     if (h->gen_n & 1) v /= std::sqrt(2.0);
-                    a[l * nr + r] = f32 ? (double)(float)v : v;
+                    cx x = v;
+                    if (gp) {
+                        x *= gtile;
+                        for (int b = 0; b < 6; b++)
+                            if ((l >> b) & 1) x *= cx(gp->lane[b][0], gp->lane[b][1]);
+                        for (int sb = 0; sb < vb; sb++)
+                            if ((r >> sb) & 1) x *= cx(gp->reg[sb][0], gp->reg[sb][1]);
+                    }
+                    a[l * nr + r] = rnd(x);
                 } else {
                     a[l * nr + r] = psi[base + roff[r] + loff[l]];
                 }

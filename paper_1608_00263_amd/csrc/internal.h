@@ -151,7 +151,25 @@ struct RTHeader {           // 128 bytes
     int32_t tq[8];          // the tile's qubits above 3 (lane qubits and
                             // register qubits), ascending: vbits + 2 entries
     int32_t fop_off;        // byte offset of the RTOpF array from the header
-    int32_t pad2[3];
+    int32_t gph_off;        // gen_n > 0 and gph_off > 0: byte offset of the
+                            // RTGenPhases of the generated state, then
+    int32_t gph_nout;       // gph_nout RTGenOut records
+    int32_t pad2;
+};
+
+// Single-qubit diagonal gates that act on the uniform state before any dense
+// gate on their qubit, folded into the generated values of the first sweep:
+// amplitude x of a tile = 2^{-n/2} c prod_{q: x_q = 1} ratio_q, with ratio_q
+// = d1/d0 of the gates on q and c the product of their d0.
+struct RTGenPhases {
+    double c[2];
+    double lane[6][2];      // ratio of the qubit on lane bit b (1: none)
+    double reg[8][2];       // ratio of the qubit in register slot s (1: none)
+};
+struct RTGenOut {           // a qubit outside the tile: its ratio applies to
+    uint64_t mask;          // the tiles whose base has the bit set
+    double r[2];
+    uint64_t pad;
 };
 
 // LDS-tile ops

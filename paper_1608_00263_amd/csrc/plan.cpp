@@ -419,6 +419,9 @@ struct RTProgram {
     std::vector<RTOp> ops;
     std::vector<DiagTerm> terms;
     std::vector<double> opc;   // cosine taken out of each op (1: none)
+    bool gen_phases = false;   // diagonals folded into the generated state
+    RTGenPhases gp{};
+    std::vector<RTGenOut> gout;
     RTProgram() { h.fscale = 1.0; }
 };
 
@@ -493,8 +496,11 @@ static std::vector<int> batch_diagonals(const std::vector<SGate> &g, const std::
     return out;
 }
 
+// gen: the sweep starts from the uniform state (generated in its registers);
+// single-qubit diagonals without a gradient slot that act before any dense
+// gate on their qubit are then folded into the generated values.
 static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int vbits, int n,
-                               bool cheap = false, int *ncheap = nullptr) {
+                               bool cheap = false, int *ncheap = nullptr, bool gen = false) {
     RTProgram P;
     RTHeader &h = P.h;
     h.vbits = vbits;
@@ -564,7 +570,55 @@ static RTProgram build_regtile(const std::vector<SGate> &g, const Sweep &sw, int
         return t;
     };
     int nc = 0;
-    for (int idx : batch_diagonals(g, sw.items)) {
+    const std::vector<int> order = batch_diagonals(g, sw.items);
+    std::vector<char> fold(order.size(), 0);
+    if (gen) {
+        // diagonals commute with each other and with CZ, so one before the
+        // first dense gate on its qubit may act first, on the uniform state
+        std::vector<char> dense_seen(64, 0);
+        cd c0 = {1.0, 0.0};
+        cd lr[6], rr[8];
+        for (auto &x : lr) x = {1.0, 0.0};
+        for (auto &x : rr) x = {1.0, 0.0};
+        std::vector<std::pair<int, cd>> outr;
+        auto mul = [](cd a, cd b) { return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; };
+        for (size_t k = 0; k < order.size(); k++) {
+            const SGate &s = g[order[k]];
+            if (s.kind == SG_DENSE) { dense_seen[s.q0] = 1; continue; }
+            if (s.kind != SG_DIAG1 || s.slot >= 0 || dense_seen[s.q0]) continue;
+            const cd d0 = s.u.m[0], d1 = s.u.m[3];
+            const double den = d0.re * d0.re + d0.im * d0.im;
+            if (den == 0.0) continue;
+            const cd ratio = {(d1.re * d0.re + d1.im * d0.im) / den, (d1.im * d0.re - d1.re * d0.im) / den};
+            c0 = mul(c0, d0);
+            if (lane_of[s.q0] >= 0) lr[lane_of[s.q0]] = mul(lr[lane_of[s.q0]], ratio);
+            else if (slot[s.q0] >= 0) rr[slot[s.q0]] = mul(rr[slot[s.q0]], ratio);
+            else {
+                size_t e = 0;
+                while (e < outr.size() && outr[e].first != s.q0) e++;
+                if (e == outr.size()) outr.push_back({s.q0, cd{1.0, 0.0}});
+                outr[e].second = mul(outr[e].second, ratio);
+            }
+            fold[k] = 1;
+            P.gen_phases = true;
+        }
+        if (P.gen_phases) {
+            P.gp.c[0] = c0.re;
+            P.gp.c[1] = c0.im;
+            for (int b = 0; b < 6; b++) { P.gp.lane[b][0] = lr[b].re; P.gp.lane[b][1] = lr[b].im; }
+            for (int r = 0; r < 8; r++) { P.gp.reg[r][0] = rr[r].re; P.gp.reg[r][1] = rr[r].im; }
+            for (auto &e : outr) {
+                RTGenOut o{};
+                o.mask = bit64(e.first);
+                o.r[0] = e.second.re;
+                o.r[1] = e.second.im;
+                P.gout.push_back(o);
+            }
+        }
+    }
+    for (size_t k = 0; k < order.size(); k++) {
+        if (fold[k]) continue;
+        const int idx = order[k];
         const SGate &s = g[idx];
         const bool in_tile = lane_of[s.q0] >= 0 || slot[s.q0] >= 0;
         if (s.kind == SG_DENSE || (s.kind == SG_DIAG1 && in_tile)) {
@@ -757,10 +811,17 @@ static void push_regtile(const RTProgram &P, int n, int dtype, OpType type, std:
         for (int j = 0; j < 8; j++) f.u[j] = (float)P.ops[i].u[j];
     }
     size_t foff = push_bytes(&plan->prog, fops.data(), fops.size() * sizeof(RTOpF));
+    size_t goff = 0;
+    if (P.gen_phases) {
+        goff = push_struct(&plan->prog, P.gp);
+        push_bytes(&plan->prog, P.gout.data(), P.gout.size() * sizeof(RTGenOut));
+    }
     RTHeader *hp = reinterpret_cast<RTHeader *>(plan->prog.data() + hoff);
     hp->op_off = (int32_t)(ooff - hoff);
     hp->term_off = (int32_t)(toff - hoff);
     hp->fop_off = (int32_t)(foff - hoff);
+    hp->gph_off = P.gen_phases ? (int32_t)(goff - hoff) : 0;
+    hp->gph_nout = (int32_t)P.gout.size();
     Op op;
     op.type = type;
     op.vbits = P.h.vbits;
@@ -770,9 +831,9 @@ static void push_regtile(const RTProgram &P, int n, int dtype, OpType type, std:
 }
 
 static void emit_regtile(const std::vector<SGate> &g, const Sweep &sw, int vbits, int n, int dtype,
-                         Plan *plan, std::vector<std::pair<size_t, int>> *scales) {
+                         Plan *plan, std::vector<std::pair<size_t, int>> *scales, bool gen = false) {
     int nc = 0;
-    RTProgram P = build_regtile(g, sw, vbits, n, true, &nc);
+    RTProgram P = build_regtile(g, sw, vbits, n, true, &nc, gen);
     push_regtile(P, n, dtype, OP_REGTILE, &plan->ops, plan);
     scales->push_back({plan->ops.back().prog_off, nc});
 }
@@ -1151,10 +1212,13 @@ sv_status build_plan(const sv_circuit *c, const PlanRequest &rq, Plan *plan) {
         vb = std::min(vb, rq.n - LANE_BITS);
         auto sweeps = regtile_sweeps(g, rq.n, vb, rq.dtype, rq.budget > 0 ? (double)rq.budget : -1.0, true);
         std::vector<std::pair<size_t, int>> scales;
-        for (const Sweep &sw : sweeps) emit_regtile(g, sw, vb, rq.n, rq.dtype, plan, &scales);
-        assign_scales(plan, scales);
         // the uniform initialisation is generated inside the first sweep's
-        // registers instead of being written and read back
+        // registers instead of being written and read back (with the
+        // diagonals that act on it folded into the generated values)
+        const bool gen = plan->ops.size() == 1 && plan->ops[0].type == OP_INIT_UNIFORM && !sweeps.empty();
+        for (size_t i = 0; i < sweeps.size(); i++)
+            emit_regtile(g, sweeps[i], vb, rq.n, rq.dtype, plan, &scales, gen && i == 0);
+        assign_scales(plan, scales);
         if (plan->ops.size() >= 2 && plan->ops[0].type == OP_INIT_UNIFORM &&
             plan->ops[1].type == OP_REGTILE) {
             RTHeader *h = reinterpret_cast<RTHeader *>(plan->prog.data() + plan->ops[1].prog_off);
