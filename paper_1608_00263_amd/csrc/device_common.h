@@ -86,28 +86,57 @@ __device__ __forceinline__ double lane_xor(double v) {
 __device__ __forceinline__ float lane_xor(float v, int m) { return __shfl_xor(v, m, 64); }
 __device__ __forceinline__ double lane_xor(double v, int m) { return __shfl_xor(v, m, 64); }
 
+// In-place butterfly of two reals: u' = u + s v, v' = t v + w u' with the
+// constants chosen per form.  Written so that each input dies where its
+// output is formed (u' from u, then v' from v and u'), the two outputs take
+// the registers of the two inputs: the straightforward form (both outputs
+// from both inputs) needs a copy per pair at the end of the op, about a third
+// of the add-only gate's instructions (measured).  v' = 2v +- u' is exact up
+// to one more rounding of u'.
+template <typename T>
+__device__ __forceinline__ void bfly_add(T &u, T &v) {   // u + v, v - u
+    u = u + v;
+    v = fma((T)2, v, -u);
+}
+template <typename T>
+__device__ __forceinline__ void bfly_sub(T &u, T &v) {   // u - v, v + u
+    u = u - v;
+    v = fma((T)2, v, u);
+}
+template <typename T>
+__device__ __forceinline__ void bfly_h(T &u, T &v) {     // u + v, u - v
+    u = u + v;
+    v = fma((T)-2, v, u);
+}
+
 // One pair (x: bit clear, y: bit set) through a gate form.
 template <typename T, int FORM>
 __device__ __forceinline__ void pair_form(cplx<T> &x, cplx<T> &y, const Mat2<T> &u) {
+    if constexpr (FORM == F_H) {               // x + y, x - y
+        bfly_h(x.re, y.re);
+        bfly_h(x.im, y.im);
+        return;
+    } else if constexpr (FORM == F_SY) {       // x - y, x + y
+        bfly_sub(x.re, y.re);
+        bfly_sub(x.im, y.im);
+        return;
+    } else if constexpr (FORM == F_SYDG) {     // x + y, y - x
+        bfly_add(x.re, y.re);
+        bfly_add(x.im, y.im);
+        return;
+    } else if constexpr (FORM == F_SX) {       // x - i y, -i x + y
+        bfly_add(x.re, y.im);                  // x.re + y.im, y.im - x.re
+        bfly_sub(x.im, y.re);                  // x.im - y.re, y.re + x.im
+        return;
+    } else if constexpr (FORM == F_SXDG) {     // x + i y, i x + y
+        bfly_sub(x.re, y.im);                  // x.re - y.im, y.im + x.re
+        bfly_add(x.im, y.re);                  // x.im + y.re, y.re - x.im
+        return;
+    }
     cplx<T> a = x, b = y;
     if constexpr (FORM == F_GEN) {
         x = cmad(u.m[1], b, cmul(u.m[0], a));
         y = cmad(u.m[3], b, cmul(u.m[2], a));
-    } else if constexpr (FORM == F_H) {
-        x.re = a.re + b.re; x.im = a.im + b.im;
-        y.re = a.re - b.re; y.im = a.im - b.im;
-    } else if constexpr (FORM == F_SY) {
-        x.re = a.re - b.re; x.im = a.im - b.im;
-        y.re = a.re + b.re; y.im = a.im + b.im;
-    } else if constexpr (FORM == F_SYDG) {
-        x.re = a.re + b.re; x.im = a.im + b.im;
-        y.re = b.re - a.re; y.im = b.im - a.im;
-    } else if constexpr (FORM == F_SX) {       // x - i y, -i x + y
-        x.re = a.re + b.im; x.im = a.im - b.re;
-        y.re = b.re + a.im; y.im = b.im - a.re;
-    } else if constexpr (FORM == F_SXDG) {     // x + i y, i x + y
-        x.re = a.re - b.im; x.im = a.im + b.re;
-        y.re = b.re - a.im; y.im = b.im + a.re;
     } else if constexpr (FORM == F_RX) {       // c x - i s y, -i s x + c y
         const T c = u.m[0].re, sn = -u.m[1].im;
         x.re = fma(c, a.re, sn * b.im); x.im = fma(c, a.im, -sn * b.re);
