@@ -828,7 +828,7 @@ def grad_timings(sv, C, torch, reps=5):
                     if ready:
                         prep()
                     t = time.perf_counter()
-                    loss, g = st.backward(circ, xs, checkpoint_c=ck, tile=tile, state_ready=ready)
+                    loss, g = st.backward(circ, xs, checkpoint_c=ck, tile=tile, state_ready=ready, args=args)
                     ts.append(time.perf_counter() - t)
                 ts = sorted(ts[1:])
                 best = ts[len(ts) // 2]

@@ -32,13 +32,14 @@ class _CircuitCrossEntropy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, circ, state, samples, checkpoint_c, stamp):
         c = circ.with_theta(theta.detach().to("cpu", torch.float64).numpy())
+        args = sv.CircuitArgs(c)   # marshalled once for both passes
         stamp.last += 1
         stamp.ready = None
         if checkpoint_c > 0:
             # the forward pass of the adjoint, keeping its state copies
-            state.forward_checkpoints(c, checkpoint_c)
+            state.forward_checkpoints(c, checkpoint_c, args=args)
         else:
-            state.apply(c, "auto", from_zero=True)
+            state.apply(c, "auto", from_zero=True, args=args)
         ce, _, zeros = state.cross_entropy(samples)
         if zeros:
             raise sv.SVError(sv.SV_ESTATE, "a sample has probability 0 under the circuit")
@@ -46,6 +47,7 @@ class _CircuitCrossEntropy(torch.autograd.Function):
         ctx.gen = stamp.last
         ctx.stamp = stamp
         ctx.circ = c
+        ctx.args = args
         ctx.state = state
         ctx.samples = samples
         ctx.checkpoint_c = checkpoint_c
@@ -61,7 +63,7 @@ class _CircuitCrossEntropy(torch.autograd.Function):
         ready = ctx.stamp.ready == ctx.gen
         ctx.stamp.ready = None
         _, grad = ctx.state.backward(ctx.circ, ctx.samples, checkpoint_c=ctx.checkpoint_c,
-                                     state_ready=ready)
+                                     state_ready=ready, args=ctx.args)
         dtype, device = ctx.theta_meta
         gt = torch.from_numpy(np.asarray(grad, dtype=np.float64)).to(device=device, dtype=dtype)
         return g.to(device=device, dtype=dtype) * gt, None, None, None, None, None

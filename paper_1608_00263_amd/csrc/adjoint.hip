@@ -251,7 +251,9 @@ __device__ __forceinline__ double lane_rot_dispatch(cplx<T> (&phi)[NR], cplx<T> 
 }
 
 // phi is read from phi_src (the state, or the checkpoint of the state after
-// the forward sweep this one reverses) and written to phi_g.  Two tiles (phi
+// the forward sweep this one reverses) and written to phi_g; store = 0 (the
+// last reverse sweep, whose gradient shares are all that is left to form)
+// writes neither phi nor mu.  Two tiles (phi
 // and mu) of 2^VB amplitudes per lane: in complex64 up to 5 register qubits
 // the kernel fits 3 waves per SIMD (168 registers in all), which the launch
 // bound keeps (two registers more left 2 waves: 24% slower, measured).
@@ -259,7 +261,8 @@ template <typename T, int VB>
 __global__ __launch_bounds__(BLOCK, (sizeof(T) == 4 && VB <= 5) ? 3 : 1) void k_regtile_adj(cplx<T> *__restrict__ phi_g, const cplx<T> *__restrict__ phi_src,
                                                        cplx<T> *__restrict__ mu_g,
                                                        const uint8_t *__restrict__ prog, uint64_t ntiles,
-                                                       double *__restrict__ gpart, int nslots) {
+                                                       double *__restrict__ gpart, int nslots,
+                                                       int store) {
     constexpr int NR = 1 << VB;
     // the program is read-only while the kernel runs: scalar loads through
     // the constant address space, also after the gradient stores
@@ -412,6 +415,7 @@ __global__ __launch_bounds__(BLOCK, (sizeof(T) == 4 && VB <= 5) ? 3 : 1) void k_
                 }
         }
     }
+    if (!store) return;
     // the cosines taken out of the tangent-form rotations
     const double fs = h->fscale;
     if (fs != 1.0) {
@@ -589,12 +593,13 @@ static sv_status backward_typed(sv_state *st, const Plan &plan, const uint64_t *
     // phi from it
     for (const Op &op : plan.bops) {
         const cplx<T> *phi_src = op.q1 >= 0 ? ckpt_ptr<T>(st, op.q1) : phi;
+        const int store = &op != &plan.bops.back();   // the states after the last one are not read
         const uint8_t *prog = (const uint8_t *)plan.dprog + op.prog_off;
         const unsigned grid = (unsigned)((ntiles + 3) / 4);
 #define ADJ_CASE(VB)                                                                                           \
     case VB:                                                                                                   \
         hipLaunchKernelGGL((k_regtile_adj<T, VB>), dim3(grid), dim3(BLOCK), 0, s, phi, phi_src, mu, prog, ntiles, \
-                           gpart, nslots);                                                                     \
+                           gpart, nslots, store);                                                              \
         break;
         switch (op.vbits) {
             ADJ_CASE(1) ADJ_CASE(2) ADJ_CASE(3) ADJ_CASE(4) ADJ_CASE(5)

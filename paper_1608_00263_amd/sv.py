@@ -324,12 +324,13 @@ class State:
         return ce.value, dh.value, z.value
 
     def backward(self, circ, samples: np.ndarray, checkpoint_c: int = 0, mode="auto", k_max=0,
-                 tile=0, state_ready=False, budget=0):
+                 tile=0, state_ready=False, budget=0, args: Optional[CircuitArgs] = None):
         """Loss and adjoint gradient; state_ready=True reuses the output state
         the handle holds (left by apply() of the same circuit, or with
         checkpoint_c > 0 by forward_checkpoints() with the same arguments)
-        instead of recomputing it."""
-        a = CircuitArgs(circ)
+        instead of recomputing it.  args: the circuit marshalled once
+        (CircuitArgs(circ)) for repeated calls."""
+        a = args or CircuitArgs(circ)
         o = make_opts(mode, k_max, tile, flags=FLAG_STATE_READY if state_ready else 0, budget=budget)
         x = np.ascontiguousarray(samples, dtype=np.uint64)
         grad = np.zeros(max(circ.nparams, 1))
