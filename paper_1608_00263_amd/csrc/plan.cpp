@@ -295,17 +295,20 @@ struct Sweep {
 // its qubits for the rest of the sweep (a skipped diagonal item blocks only
 // non-diagonal items on its qubits, since diagonal items commute).
 //
-// Two groupings are built and the one with fewer sweeps kept: gathered sets
-// grown greedily in list order; and, per sweep, the best (by items taken)
-// of that greedy set and the `cap` qubits carrying the most non-diagonal
-// items among the next W pending items, for a few look-ahead windows W.
+// Three groupings are built and the one with fewer sweeps kept: gathered
+// sets grown greedily in list order; per sweep, the best (by items taken) of
+// that greedy set and the `cap` qubits carrying the most non-diagonal items
+// among the next W pending items, for a few look-ahead windows W; and a beam
+// search (beam > 1) that keeps the `beam` partial groupings with the most
+// items taken after each sweep, each extended by all of those candidates.
 static std::vector<Sweep> group_sweeps_once(bool lookahead, int nfixed, int nitems, int n, int cap,
                                             const std::function<bool(int)> &diag,
                                             const std::function<std::vector<int>(int)> &qubits,
                                             const std::function<double(int, const std::vector<char> &)> &cost,
-                                            double budget) {
+                                            double budget, int beam = 1) {
     std::vector<Sweep> out;
-    std::vector<char> done(nitems, 0);
+    std::vector<char> done0(nitems, 0);
+    const std::vector<char> *cur = &done0;   // the items already taken
     int left = nitems;
     std::vector<std::vector<int>> qs_of(nitems);
     std::vector<char> is_diag(nitems);
@@ -327,7 +330,7 @@ static std::vector<Sweep> group_sweeps_once(bool lookahead, int nfixed, int nite
                 if ((*fixed)[q]) { in_tile[q] = 1; sw->tile.push_back(q); ngather++; }
         double spent = 0;
         for (int i = 0; i < nitems; i++) {
-            if (done[i]) continue;
+            if ((*cur)[i]) continue;
             const std::vector<int> &qs = qs_of[i];
             const bool d = is_diag[i];
             bool ok = true;
@@ -360,15 +363,16 @@ static std::vector<Sweep> group_sweeps_once(bool lookahead, int nfixed, int nite
         }
         std::sort(sw->tile.begin(), sw->tile.end());
     };
-    while (left > 0) {
-        Sweep best;
-        simulate(nullptr, &best);
-        for (int W : {24, 48, 96, 192}) {
-            if (!lookahead) break;
+    // candidate sweeps from the current state: the greedy one and, with
+    // look-ahead, one per window W
+    auto candidates = [&](const std::vector<int> &windows) {
+        std::vector<Sweep> cs(1);
+        simulate(nullptr, &cs[0]);
+        for (int W : windows) {
             std::vector<int> count(n, 0), first(n, nitems);
             int seen = 0;
             for (int i = 0; i < nitems && seen < W; i++) {
-                if (done[i]) continue;
+                if ((*cur)[i]) continue;
                 seen++;
                 if (is_diag[i]) continue;
                 for (int q : qs_of[i])
@@ -388,16 +392,62 @@ static std::vector<Sweep> group_sweeps_once(bool lookahead, int nfixed, int nite
             for (int q : cand) fixed[q] = 1;
             Sweep sw;
             simulate(&fixed, &sw);
-            if (sw.items.size() > best.items.size()) best = sw;
+            cs.push_back(sw);
         }
-        // an item that fits no sweep (wider than the tile) would never be
-        // taken: no grouping
-        if (best.items.empty()) return {};
-        for (int i : best.items) done[i] = 1;
-        left -= (int)best.items.size();
-        out.push_back(best);
+        return cs;
+    };
+    if (beam <= 1) {
+        std::vector<int> windows;
+        if (lookahead) windows = {24, 48, 96, 192};
+        while (left > 0) {
+            std::vector<Sweep> cs = candidates(windows);
+            Sweep best = cs[0];
+            for (size_t c = 1; c < cs.size(); c++)
+                if (cs[c].items.size() > best.items.size()) best = cs[c];
+            // an item that fits no sweep (wider than the tile) would never be
+            // taken: no grouping
+            if (best.items.empty()) return {};
+            for (int i : best.items) done0[i] = 1;
+            left -= (int)best.items.size();
+            out.push_back(best);
+        }
+        return out;
     }
-    return out;
+    struct State {
+        std::vector<char> done;
+        std::vector<Sweep> sweeps;
+        int left;
+    };
+    std::vector<State> states(1);
+    states[0].done.assign(nitems, 0);
+    states[0].left = nitems;
+    const std::vector<int> windows = {12, 24, 36, 48, 72, 96, 144, 192, 288};
+    for (;;) {
+        for (const State &st : states)
+            if (st.left == 0) return st.sweeps;
+        std::vector<State> next;
+        for (const State &st : states) {
+            cur = &st.done;
+            for (const Sweep &sw : candidates(windows)) {
+                if (sw.items.empty()) continue;
+                State c;
+                c.done = st.done;
+                for (int i : sw.items) c.done[i] = 1;
+                bool dup = false;
+                for (const State &o : next)
+                    if (o.done == c.done) { dup = true; break; }
+                if (dup) continue;
+                c.sweeps = st.sweeps;
+                c.sweeps.push_back(sw);
+                c.left = st.left - (int)sw.items.size();
+                next.push_back(std::move(c));
+            }
+        }
+        if (next.empty()) return {};
+        std::stable_sort(next.begin(), next.end(), [](const State &a, const State &b) { return a.left < b.left; });
+        if ((int)next.size() > beam) next.resize(beam);
+        states.swap(next);
+    }
 }
 
 // nfixed: qubits 0..nfixed-1 are always in the sweep's set (the lanes).
@@ -409,7 +459,10 @@ static std::vector<Sweep> group_sweeps(int nitems, int n, int cap, const std::fu
     std::vector<Sweep> a = group_sweeps_once(false, nfixed, nitems, n, cap, diag, qubits, cost, budget);
     std::vector<Sweep> b = group_sweeps_once(true, nfixed, nitems, n, cap, diag, qubits, cost, budget);
     if (a.empty() || b.empty()) return a.empty() ? b : a;   // empty: some item fits no sweep
-    return b.size() < a.size() ? b : a;
+    std::vector<Sweep> best = b.size() < a.size() ? b : a;
+    std::vector<Sweep> c = group_sweeps_once(true, nfixed, nitems, n, cap, diag, qubits, cost, budget, 6);
+    if (!c.empty() && c.size() < best.size()) best = c;
+    return best;
 }
 
 static uint64_t bit64(int q) { return (uint64_t)1 << q; }
