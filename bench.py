@@ -123,8 +123,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="regtile")
-    ap.add_argument("--tile", type=int, default=6)
+    ap.add_argument("--mode", default="auto", help="planning mode of the timed steps (default: the autotuner)")
+    ap.add_argument("--tile", type=int, default=0, help="register qubits for --mode regtile (0: default)")
     ap.add_argument("--samples", type=int, default=100000)
     ap.add_argument("--no-modes", action="store_true", help="skip the per-mode circuit timings")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint timing")
@@ -236,6 +236,16 @@ def main():
     args = sv.CircuitArgs(circ)
     st = sv.State(n, "c64")
     m = a.samples
+    # the autotuner's choice is made once, before the warm-up (it times its
+    # candidates on a scratch state), so no timed step includes tuning
+    choice = None
+    rt_tile = a.tile or 6
+    if a.mode == "auto":
+        cname, ck, ctile, complete, cbudget = st.autotune(circ, from_zero=True)
+        choice = {"mode": cname, "k_max": ck, "tile": ctile, "sweep_budget": cbudget, "complete": complete}
+        if cname == "regtile":
+            rt_tile = ctile or 6
+        log("autotuner: %s" % choice)
 
     def step():
         ms, kinds, by = st.apply_timed(circ, a.mode, 0, a.tile, args=args, from_zero=True)
@@ -271,7 +281,7 @@ def main():
     step_bytes = sweep_bytes[-1] + S64 + m * 128.0
     value = step_bytes / step_s / 1e9
     achieved = dom_bytes / (dom_ms / 1e3) / 1e9
-    floor = sweep_floor(sv, C, st, a.tile if a.mode == "regtile" else 6)
+    floor = sweep_floor(sv, C, st, rt_tile)
     log("timed %d steps: %.2f ms/step, sweeps %.2f ms, %d sweeps" % (a.steps, step_s * 1e3,
                                                                         np.mean(sweep_ms), nsweeps))
     out = {
@@ -289,15 +299,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "random lattice circuit, 5x6 grid = 30 qubits, depth 40 (625 gates), "
                                "complex64 state, statistics + 1e5 samples + their cross entropy",
-                   "mode": a.mode, "register_qubits": a.tile, "sweeps": nsweeps},
+                   "mode": a.mode, "choice": choice, "register_qubits": rt_tile, "sweeps": nsweeps},
         "sweep_GBps": round(sweep_bytes[-1] / (np.mean(sweep_ms) / 1e3) / 1e9, 2),
         "sweep_frac_of_peak": round(sweep_bytes[-1] / (np.mean(sweep_ms) / 1e3) / 1e9 / PEAK_HBM_GBPS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(a.tile if a.mode == "regtile" else -1),
-                     "kernel": "k_regtile<float,%d>" % a.tile,
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(rt_tile),
+                     "kernel": "k_regtile<float,%d>" % rt_tile,
                      "launch_avg_ms": round(dom_ms / max(dom_launches, 1), 4),
                      "bytes_per_launch": round(dom_bytes / max(dom_launches, 1), 1),
-                     "valu_frac": measured_valu_frac(a.tile if a.mode == "regtile" else -1),
+                     "valu_frac": measured_valu_frac(rt_tile),
                      "achievable": floor["GBps"], "frac_of_achievable": round(achieved / floor["GBps"], 4),
                      "achievable_how": floor["how"],
                      "kernel_sources_sha1": kernel_sha1()},
@@ -371,16 +381,18 @@ def copy_probe(torch):
 
 
 def roofline_c128(sv, C, circ, torch, reps=5):
-    """The complex128 register-tile sweep (5 register qubits) on the same
-    30-qubit circuit: algorithmic bytes per launch over the HIP-event average
-    duration of its launches, median circuit of reps runs."""
+    """The complex128 register-tile sweep on the same 30-qubit circuit, as
+    the autotuner plans it: algorithmic bytes per launch over the HIP-event
+    average duration of its launches, median circuit of reps runs."""
     import numpy as np
     st = sv.State(circ.n, "c128")
     args = sv.CircuitArgs(circ)
-    st.apply_timed(circ, "regtile", 0, 5, args=args, from_zero=True)
+    cname, ck, ctile, complete, cbudget = st.autotune(circ, from_zero=True)
+    choice = {"mode": cname, "k_max": ck, "tile": ctile, "sweep_budget": cbudget}
+    st.apply_timed(circ, "auto", 0, 0, args=args, from_zero=True)
     runs = []
     for _ in range(reps):
-        ms, kinds, by = st.apply_timed(circ, "regtile", 0, 5, args=args, from_zero=True)
+        ms, kinds, by = st.apply_timed(circ, "auto", 0, 0, args=args, from_zero=True)
         sel = kinds == 8
         runs.append((float(ms[sel].sum()), float(by[sel].sum()), int(sel.sum()), float(ms.sum())))
     runs.sort()
@@ -390,9 +402,11 @@ def roofline_c128(sv, C, circ, torch, reps=5):
     del st
     torch.cuda.empty_cache()
     log("c128 register tiles: %.2f ms, %d sweeps, %.0f GB/s" % (tot, nl, achieved))
+    tile = (ctile or 5) if cname == "regtile" else 5
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(5, TRAFFIC_FILE_C128),
-            "valu_frac": measured_valu_frac(5, TRAFFIC_FILE_C128), "kernel": "k_regtile<double,5>",
+            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(tile, TRAFFIC_FILE_C128),
+            "valu_frac": measured_valu_frac(tile, TRAFFIC_FILE_C128), "kernel": "k_regtile<double,%d>" % tile,
+            "choice": choice,
             "launches": nl, "launch_avg_ms": round(dom_ms / nl, 4), "bytes_per_launch": round(dom_by / nl, 1),
             "circuit_ms": round(tot, 3), "workload": "5x6 grid, 30 qubits, depth 40, complex128 (16 GiB)"}
 

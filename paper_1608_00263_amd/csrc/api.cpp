@@ -87,10 +87,21 @@ static std::map<std::string, sv_opts> g_tuned;   // process-wide choices
 
 static std::vector<sv_opts> tune_candidates(const sv_state *st) {
     std::vector<sv_opts> c;
-    auto add = [&](int mode, int k, int t) { c.push_back(sv_opts{mode, k, t, 0, 0}); };
+    auto add = [&](int mode, int k, int t, int budget = 0) { c.push_back(sv_opts{mode, k, t, 0, budget, 0}); };
     if (st->n >= 10) {
-        if (st->dt == SV_C64) { add(SV_MODE_REGTILE, 0, 4); add(SV_MODE_REGTILE, 0, 5); add(SV_MODE_REGTILE, 0, 6); }
-        else { add(SV_MODE_REGTILE, 0, 3); add(SV_MODE_REGTILE, 0, 4); add(SV_MODE_REGTILE, 0, 5); }
+        // register tiles of each width at the default sweep budget, and the
+        // widest also at a smaller budget: lighter sweeps, sometimes one more
+        // of them (which is faster depends on the circuit: measured on the
+        // 30-qubit depth-40 circuit 42.3 against 43.4 ms in complex64, 95.2
+        // against 97.8 ms in complex128, on the 35-qubit one 1.68 against
+        // 1.61 s)
+        if (st->dt == SV_C64) {
+            add(SV_MODE_REGTILE, 0, 4); add(SV_MODE_REGTILE, 0, 5); add(SV_MODE_REGTILE, 0, 6);
+            add(SV_MODE_REGTILE, 0, 6, 160);
+        } else {
+            add(SV_MODE_REGTILE, 0, 3); add(SV_MODE_REGTILE, 0, 4); add(SV_MODE_REGTILE, 0, 5);
+            add(SV_MODE_REGTILE, 0, 5, 140);
+        }
         add(SV_MODE_FUSED, 2, 0);
         add(SV_MODE_FUSED, 3, 0);
         // complex64 LDS tiles of dense 8x8 blocks are bound by the FP32 VALU
@@ -156,9 +167,13 @@ static sv_status resolve_auto(sv_state *st, const sv_circuit *c, bool from_zero,
             rq.from_zero = from_zero;
             std::shared_ptr<Plan> plan;
             rc = get_plan(st, c, rq, &plan);
-            float ms = 0;
+            float ms = 0, m1 = 0;
             if (rc == SV_OK) rc = time_plan(st, *plan, scratch, &ms);           // warm
-            if (rc == SV_OK) rc = time_plan(st, *plan, scratch, &ms);
+            // best of three: candidates a few percent apart stay ordered
+            for (int r = 0; r < 3 && rc == SV_OK; r++) {
+                rc = time_plan(st, *plan, scratch, &m1);
+                if (r == 0 || m1 < ms) ms = m1;
+            }
             if (rc == SV_OK && (best < 0 || ms < best_ms)) { best = (int)i; best_ms = ms; }
         }
         (void)hipStreamSynchronize(st->stream);
