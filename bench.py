@@ -39,6 +39,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
+# the library's register-tile sweep budget when the options leave it 0
+DEFAULT_SWEEP_BUDGET = {"c64": 250, "c128": 220}
 PEAK_FP32_MFMA_TFLOPS = 157.3   # dense FP32 matrix peak of the MI355X
 PEAK_FP64_MFMA_TFLOPS = 78.6    # dense FP64 matrix peak of the MI355X
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_regtile_c2_traffic.txt")
@@ -74,25 +76,27 @@ def read_summary(path):
         return {}
 
 
-def profile_summary(tile, path=TRAFFIC_FILE):
-    """The register-tile counter summary for this tile width, or {}."""
+def profile_summary(tile, budget, path=TRAFFIC_FILE):
+    """The register-tile counter summary for this tile width and sweep
+    budget (the plan whose launches it counted), or {}."""
     kv = read_summary(path)
     try:
-        return kv if int(kv.get("register_qubits", -1)) == tile else {}
+        same = int(kv.get("register_qubits", -1)) == tile and int(kv.get("sweep_budget", -1)) == budget
     except ValueError:
         return {}
+    return kv if same else {}
 
 
-def measured_traffic(tile, path=TRAFFIC_FILE):
+def measured_traffic(tile, budget, path=TRAFFIC_FILE):
     """HBM bytes per register-tile launch from the counter summary, or None."""
-    v = profile_summary(tile, path).get("traffic_bytes_per_launch")
+    v = profile_summary(tile, budget, path).get("traffic_bytes_per_launch")
     return float(v) if v is not None else None
 
 
-def measured_valu_frac(tile, path=TRAFFIC_FILE):
+def measured_valu_frac(tile, budget, path=TRAFFIC_FILE):
     """Vector-ALU issue share of the register-tile sweeps from the counter
     summary (instructions over one per CU-cycle at 2.4 GHz), or None."""
-    v = profile_summary(tile, path).get("valu_frac")
+    v = profile_summary(tile, budget, path).get("valu_frac")
     return float(v) if v is not None else None
 
 
@@ -125,6 +129,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="auto", help="planning mode of the timed steps (default: the autotuner)")
     ap.add_argument("--tile", type=int, default=0, help="register qubits for --mode regtile (0: default)")
+    ap.add_argument("--budget", type=int, default=0, help="sweep budget for --mode regtile (0: default)")
+    ap.add_argument("--c128-budget", type=int, default=0,
+                    help="complex128 roofline: 5-qubit register tiles at this sweep budget (0: the autotuner)")
     ap.add_argument("--samples", type=int, default=100000)
     ap.add_argument("--no-modes", action="store_true", help="skip the per-mode circuit timings")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint timing")
@@ -240,15 +247,17 @@ def main():
     # candidates on a scratch state), so no timed step includes tuning
     choice = None
     rt_tile = a.tile or 6
+    rt_budget = a.budget or DEFAULT_SWEEP_BUDGET["c64"]
     if a.mode == "auto":
         cname, ck, ctile, complete, cbudget = st.autotune(circ, from_zero=True)
         choice = {"mode": cname, "k_max": ck, "tile": ctile, "sweep_budget": cbudget, "complete": complete}
         if cname == "regtile":
             rt_tile = ctile or 6
+            rt_budget = cbudget or DEFAULT_SWEEP_BUDGET["c64"]
         log("autotuner: %s" % choice)
 
     def step():
-        ms, kinds, by = st.apply_timed(circ, a.mode, 0, a.tile, args=args, from_zero=True)
+        ms, kinds, by = st.apply_timed(circ, a.mode, 0, a.tile, args=args, from_zero=True, budget=a.budget)
         mom, xs = st.moments_and_sample(m, 1002)
         ce, dh, z = st.cross_entropy(xs, norm=mom["norm"])
         return ms, kinds, by, mom, ce, dh
@@ -299,15 +308,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "random lattice circuit, 5x6 grid = 30 qubits, depth 40 (625 gates), "
                                "complex64 state, statistics + 1e5 samples + their cross entropy",
-                   "mode": a.mode, "choice": choice, "register_qubits": rt_tile, "sweeps": nsweeps},
+                   "mode": a.mode, "choice": choice, "register_qubits": rt_tile, "sweep_budget": rt_budget,
+                   "sweeps": nsweeps},
         "sweep_GBps": round(sweep_bytes[-1] / (np.mean(sweep_ms) / 1e3) / 1e9, 2),
         "sweep_frac_of_peak": round(sweep_bytes[-1] / (np.mean(sweep_ms) / 1e3) / 1e9 / PEAK_HBM_GBPS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(rt_tile),
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(rt_tile, rt_budget),
                      "kernel": "k_regtile<float,%d>" % rt_tile,
                      "launch_avg_ms": round(dom_ms / max(dom_launches, 1), 4),
                      "bytes_per_launch": round(dom_bytes / max(dom_launches, 1), 1),
-                     "valu_frac": measured_valu_frac(rt_tile),
+                     "valu_frac": measured_valu_frac(rt_tile, rt_budget),
                      "achievable": floor["GBps"], "frac_of_achievable": round(achieved / floor["GBps"], 4),
                      "achievable_how": floor["how"],
                      "kernel_sources_sha1": kernel_sha1()},
@@ -320,7 +330,7 @@ def main():
     del st
     torch.cuda.empty_cache()
     if not a.no_c128_roofline:
-        out["roofline_c128"] = roofline_c128(sv, C, circ, torch)
+        out["roofline_c128"] = roofline_c128(sv, C, circ, torch, a.c128_budget)
     if not a.no_modes:
         only = set(x for x in a.modes.split(",") if x)
         out["circuit_s"] = mode_timings(sv, C, circ, torch, only)
@@ -380,19 +390,24 @@ def copy_probe(torch):
     return {"bytes": 2 * 8.0 * 2 ** 30, "s": round(dt, 5), "GBps": round(2 * 8.0 * 2 ** 30 / dt / 1e9, 1)}
 
 
-def roofline_c128(sv, C, circ, torch, reps=5):
+def roofline_c128(sv, C, circ, torch, budget=0, reps=5):
     """The complex128 register-tile sweep on the same 30-qubit circuit, as
-    the autotuner plans it: algorithmic bytes per launch over the HIP-event
-    average duration of its launches, median circuit of reps runs."""
+    the autotuner plans it (budget > 0: 5-qubit tiles at that sweep budget):
+    algorithmic bytes per launch over the HIP-event average duration of its
+    launches, median circuit of reps runs."""
     import numpy as np
     st = sv.State(circ.n, "c128")
     args = sv.CircuitArgs(circ)
-    cname, ck, ctile, complete, cbudget = st.autotune(circ, from_zero=True)
+    if budget > 0:
+        cname, ck, ctile, cbudget = "regtile", 0, 5, budget
+    else:
+        cname, ck, ctile, complete, cbudget = st.autotune(circ, from_zero=True)
     choice = {"mode": cname, "k_max": ck, "tile": ctile, "sweep_budget": cbudget}
-    st.apply_timed(circ, "auto", 0, 0, args=args, from_zero=True)
+    run = ("regtile", 0, 5, budget) if budget > 0 else ("auto", 0, 0, 0)
+    st.apply_timed(circ, run[0], run[1], run[2], args=args, from_zero=True, budget=run[3])
     runs = []
     for _ in range(reps):
-        ms, kinds, by = st.apply_timed(circ, "auto", 0, 0, args=args, from_zero=True)
+        ms, kinds, by = st.apply_timed(circ, run[0], run[1], run[2], args=args, from_zero=True, budget=run[3])
         sel = kinds == 8
         runs.append((float(ms[sel].sum()), float(by[sel].sum()), int(sel.sum()), float(ms.sum())))
     runs.sort()
@@ -403,9 +418,10 @@ def roofline_c128(sv, C, circ, torch, reps=5):
     torch.cuda.empty_cache()
     log("c128 register tiles: %.2f ms, %d sweeps, %.0f GB/s" % (tot, nl, achieved))
     tile = (ctile or 5) if cname == "regtile" else 5
+    tb = cbudget or DEFAULT_SWEEP_BUDGET["c128"]
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(tile, TRAFFIC_FILE_C128),
-            "valu_frac": measured_valu_frac(tile, TRAFFIC_FILE_C128), "kernel": "k_regtile<double,%d>" % tile,
+            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(tile, tb, TRAFFIC_FILE_C128),
+            "valu_frac": measured_valu_frac(tile, tb, TRAFFIC_FILE_C128), "kernel": "k_regtile<double,%d>" % tile,
             "choice": choice,
             "launches": nl, "launch_avg_ms": round(dom_ms / nl, 4), "bytes_per_launch": round(dom_by / nl, 1),
             "circuit_ms": round(tot, 3), "workload": "5x6 grid, 30 qubits, depth 40, complex128 (16 GiB)"}

@@ -253,7 +253,8 @@ class State:
         return ms[:m], kinds[:m], by[:m]
 
     def autotune(self, circ, from_zero=True):
-        """Run the autotuner for circ; returns (mode name, k_max, tile, complete)."""
+        """Run the autotuner for circ; returns (mode name, k_max, tile, complete,
+        sweep budget)."""
         a = CircuitArgs(circ)
         o = Opts()
         done = ctypes.c_int()
