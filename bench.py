@@ -2,7 +2,9 @@
 
 One step = the whole path over one synthetic input: simulate the 5x6-grid,
 30-qubit, depth-40 random circuit of Sec. IV from |0...0> in complex64
-(fused register-tile sweeps), compute the output statistics (entropy,
+with the plan the autotuner picks once before the warm-up (register-tile
+sweeps on this circuit; --mode/--tile/--budget pin a plan), compute the
+output statistics (entropy,
 uniform cross entropy, moments 1..10), draw 10^5 samples and evaluate
 their cross entropy.  Prints one JSON line.
 
@@ -17,7 +19,8 @@ circuit_s  = seconds of the same circuit per planning mode (plain per-gate,
              specialised per-gate, fused 2^k blocks, LDS tiles, register
              tiles) in complex64 and complex128;
 roofline_c128 = the same for the complex128 register-tile sweep
-             (k_regtile<double,5>) on the same circuit;
+             (k_regtile<double,5>) on the same circuit, as the
+             autotuner plans it (--c128-budget pins a sweep budget);
 grad       = adjoint gradient time over forward time on the 5x5, depth-30
              parametrised circuit (10^4 samples) for checkpoint intervals;
 cycles     = statistics after every cycle (Sec. IV) and the first cycle
