@@ -63,6 +63,28 @@ def test_c1_amplitudes(c1, mode, k, t, dtype):
     assert np.linalg.norm(out - ref) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("budget", [20, 60, 140, 160, 400, 2000])
+def test_regtile_sweep_budgets(c1, budget):
+    # register tiles at sweep budgets across the allowed range (the two the
+    # autotuner adds, 160 for complex64 and 140 for complex128, among them),
+    # the 16-qubit circuit from |0..0> and a 20-qubit paper circuit
+    circ, ref = c1
+    for dtype, tile in (("c64", 6), ("c128", 5)):
+        st = sv.State(circ.n, dtype)
+        st.apply(circ, "regtile", 0, tile, from_zero=True, budget=budget)
+        out = st.amplitudes().astype(np.complex128)
+        st.close()
+        assert np.linalg.norm(out - ref) <= TOL[dtype], (dtype, budget)
+    c20 = C.make_circuit(4, 5, 30, seed=4)
+    ref20 = oracle.apply_circuit(c20)
+    for dtype, tile in (("c64", 6), ("c128", 5)):
+        st = sv.State(c20.n, dtype)
+        st.apply(c20, "regtile", 0, tile, from_zero=True, budget=budget)
+        out = st.amplitudes().astype(np.complex128)
+        st.close()
+        assert np.linalg.norm(out - ref20) <= TOL[dtype], (dtype, budget, c20.n)
+
+
 @pytest.mark.parametrize("mode,k,t", MODES)
 def test_random_kinds_from_random_state(mode, k, t):
     # all gate kinds, dense U1 gates, CZ on arbitrary pairs, arbitrary start

@@ -75,6 +75,35 @@ def test_plan_replay_random_kinds(mode, k, t):
     assert np.linalg.norm(out - ref) < 1e-12
 
 
+@pytest.mark.parametrize("budget", [20, 60, 160, 400, 2000])
+@pytest.mark.parametrize("dtype,tile", [("c64", 6), ("c64", 4), ("c128", 5)])
+def test_plan_replay_regtile_budgets(budget, dtype, tile):
+    # the register-tile grouping at sweep budgets across the allowed range
+    # (greedy, look-ahead and beam groupings, whichever needs fewest sweeps)
+    circ = C.make_circuit(3, 5, 30, seed=3)
+    ref = oracle.apply_circuit(circ)
+    psi0 = np.zeros(1 << circ.n, complex)
+    psi0[0] = 1
+    out = sv.host_emulate(circ, psi0, dtype, "regtile", 0, tile, budget=budget)
+    tol = 1e-5 if dtype == "c64" else 1e-12
+    assert np.linalg.norm(out - ref) < tol
+    rnd = C.random_unitary_circuit(12, 160, seed=78)
+    p0 = C.random_state(12, 6, dtype=np.complex128)
+    ref = oracle.apply_circuit(rnd, p0.copy())
+    out = sv.host_emulate(rnd, p0, dtype, "regtile", 0, min(tile, 6), from_zero=False, budget=budget)
+    assert np.linalg.norm(out - ref) < tol
+
+
+def test_plan_sweep_budget_bounds():
+    circ = C.make_circuit(3, 4, 10, seed=1)
+    for bad in (1, 19, 2001):
+        with pytest.raises(sv.SVError) as e:
+            sv.host_plan(circ, "c64", "regtile", 0, 5, budget=bad)
+        assert e.value.status == sv.SV_EINVAL
+    for good in (20, 2000):
+        assert sv.host_plan(circ, "c64", "regtile", 0, 5, budget=good)["sweeps"] > 0
+
+
 def test_plan_replay_parametrised():
     circ = C.make_circuit(3, 4, 16, seed=8, parametrise=True, theta_seed=9, theta_std=0.3)
     ref = oracle.apply_circuit(circ)
