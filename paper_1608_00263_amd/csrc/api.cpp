@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <limits>
 #include <cstdio>
 #include <cstdlib>
 #include <new>
@@ -142,6 +143,15 @@ static sv_status time_plan(sv_state *st, const Plan &plan, void *psi, float *ms)
     return rc;
 }
 
+// A plan cannot run faster than its algorithmic bytes at the HBM peak
+// (8 TB/s): a candidate whose bound exceeds the best measured time is not
+// timed.
+static double plan_floor_ms(const Plan &plan) {
+    double b = 0;
+    for (const Op &op : plan.ops) b += op.bytes;
+    return b / 8.0e9;
+}
+
 // Resolve SV_MODE_AUTO to concrete options for (st, c).  May run the
 // scratch-state tuning; sets *explore when this call should instead time a
 // candidate on the real state.
@@ -167,6 +177,7 @@ static sv_status resolve_auto(sv_state *st, const sv_circuit *c, bool from_zero,
             rq.from_zero = from_zero;
             std::shared_ptr<Plan> plan;
             rc = get_plan(st, c, rq, &plan);
+            if (rc == SV_OK && best >= 0 && plan_floor_ms(*plan) > best_ms) continue;
             float ms = 0, m1 = 0;
             if (rc == SV_OK) rc = time_plan(st, *plan, scratch, &ms);           // warm
             // best of three: candidates a few percent apart stay ordered
@@ -186,6 +197,16 @@ static sv_status resolve_auto(sv_state *st, const sv_circuit *c, bool from_zero,
     // no room for a scratch state: explore on the real calls
     Tune &t = st->tunes[key];
     if (t.cand.empty()) { t.cand = cand; t.ms.assign(cand.size(), 0.0); }
+    while (t.next > 0 && t.next < t.cand.size()) {
+        double best_ms = t.ms[0];
+        for (size_t i = 1; i < t.next; i++) best_ms = std::min(best_ms, t.ms[i]);
+        PlanRequest rq = make_request(st, &t.cand[t.next]);
+        rq.from_zero = from_zero;
+        std::shared_ptr<Plan> plan;
+        SV_TRY(get_plan(st, c, rq, &plan));
+        if (plan_floor_ms(*plan) <= best_ms) break;
+        t.ms[t.next++] = std::numeric_limits<double>::infinity();   // cannot win: not run
+    }
     if (t.next < t.cand.size()) {
         *explore = (int)t.next;
         *out = t.cand[t.next];

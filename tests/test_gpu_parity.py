@@ -598,6 +598,26 @@ def test_sample_from_statuses():
             oracle.sample_from_words(np.array(vals), C.splitmix64_words(5, 64))
 
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_autotune_choice_and_auto_result(dtype):
+    # the autotuner on a 20-qubit paper circuit: a complete choice among its
+    # candidates (register tiles win on these circuits; per-gate and fused
+    # plans are not even timed when their bytes at the HBM peak exceed the
+    # best time), the same choice on a second call, and the AUTO result
+    # against the oracle
+    circ = C.make_circuit(4, 5, 30, seed=6)
+    ref = oracle.apply_circuit(circ)
+    st = sv.State(circ.n, dtype)
+    first = st.autotune(circ, from_zero=True)
+    again = st.autotune(circ, from_zero=True)
+    assert first == again and first[3] is True, (first, again)
+    assert first[0] in ("regtile", "fused", "tiled"), first
+    st.apply(circ, "auto", from_zero=True)
+    out = st.amplitudes().astype(np.complex128)
+    st.close()
+    assert np.linalg.norm(out - ref) <= TOL[dtype]
+
+
 def test_attached_buffer_written_after_reset():
     # reset() of a caller-owned buffer, then the caller writes it: the next
     # circuit must act on what the caller wrote, not on |0..0>
