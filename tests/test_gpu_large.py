@@ -274,6 +274,33 @@ def test_c5_circuit_then_inverse_is_identity(st35):
     assert p0 > 1.0 - 1e-4
 
 
+def test_c5_auto_explores_on_the_callers_calls(st35):
+    # a 256 GiB state leaves no room for a scratch copy, so the autotuner
+    # times its candidates on the caller's own calls, one per call; the four
+    # register-tile candidates are run, the fused ones (12 and 8 s at the
+    # HBM peak against about 2 s measured) are skipped; every call leaves
+    # the circuit's output state
+    circ = C.make_circuit(5, 7, 40, seed=5)
+    st35.apply(circ, "regtile", 0, 6, from_zero=True)
+    ref = st35.moments()
+    calls = 0
+    while True:
+        choice = st35.autotune(circ, from_zero=True)
+        if choice[3]:
+            break
+        st35.apply(circ, "auto", from_zero=True)
+        calls += 1
+        m = st35.moments()
+        print("auto call %d (%s tile %d budget %d): entropy %.9f" % (calls, choice[0], choice[2], choice[4],
+                                                                   m["entropy"]), flush=True)
+        assert abs(m["entropy"] - ref["entropy"]) < 1e-4 and abs(m["norm"] - 1.0) < 1e-5
+        assert calls <= 6
+    assert calls == 4 and choice[0] == "regtile", (calls, choice)
+    st35.apply(circ, "auto", from_zero=True)
+    m = st35.moments()
+    assert abs(m["entropy"] - ref["entropy"]) < 1e-4 and abs(m["norm"] - 1.0) < 1e-5
+
+
 def test_c5_porter_thomas_and_sample_cross_entropy(st35):
     # Statistics after every cycle.  sigma_H = 0.5385 2^{-n/2} nats is the
     # spread of the entropy of Porter-Thomas (Dirichlet) vectors.  An error
