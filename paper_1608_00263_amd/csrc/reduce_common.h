@@ -62,6 +62,15 @@ constexpr int NSTAT = 13;   // S, sum p ln p, sum ln p, sum u^k (k = 1..10)
 // 2 (s + s^3/3 + ... + s^19/19); the first omitted term is below 3e-17 of
 // ln m.  ln 2 is split into a 32-bit head, so e * LN2_HI is exact, and the
 // remainder.  ln 1 = 0 exactly.
+// a * b + c as the three-operand FP64 FMA: the series coefficients stay in
+// registers across the loop, where the accumulating form (whose addend is
+// also its destination) would copy each coefficient before every use
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 __device__ __forceinline__ double ln_pos(double x) {
     constexpr double LN2_HI = 6.93147180369123816490e-01;   // 0x3fe62e42fee00000
     constexpr double LN2_LO = 1.90821492927058770002e-10;   // ln 2 - LN2_HI
@@ -79,14 +88,14 @@ __device__ __forceinline__ double ln_pos(double x) {
     s = fma(fma(-s, d, f), r, s);                           // s = f / d, corrected
     const double z = s * s;
     double q = 2.0 / 19.0;
-    q = fma(q, z, 2.0 / 17.0);
-    q = fma(q, z, 2.0 / 15.0);
-    q = fma(q, z, 2.0 / 13.0);
-    q = fma(q, z, 2.0 / 11.0);
-    q = fma(q, z, 2.0 / 9.0);
-    q = fma(q, z, 2.0 / 7.0);
-    q = fma(q, z, 2.0 / 5.0);
-    q = fma(q, z, 2.0 / 3.0);
+    q = fma3(q, z, 2.0 / 17.0);
+    q = fma3(q, z, 2.0 / 15.0);
+    q = fma3(q, z, 2.0 / 13.0);
+    q = fma3(q, z, 2.0 / 11.0);
+    q = fma3(q, z, 2.0 / 9.0);
+    q = fma3(q, z, 2.0 / 7.0);
+    q = fma3(q, z, 2.0 / 5.0);
+    q = fma3(q, z, 2.0 / 3.0);
     const double lnm = fma(s * z, q, s + s);
     const double de = (double)e;
     return fma(de, LN2_HI, fma(de, LN2_LO, lnm));
