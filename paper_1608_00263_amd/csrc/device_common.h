@@ -27,6 +27,23 @@ __device__ __forceinline__ cplx<T> cmul(cplx<T> u, cplx<T> x) {
     return r;
 }
 
+// x <- u x in place, with the same roundings as cmul.  In FP32 the two
+// products go to temporaries and the two multiply-adds write back into the
+// registers of x: the accumulating multiply-add the compiler picks otherwise
+// writes its result over the addend (a temporary), which moves every output
+// one register along and ends a multiply op over a tile in a run of copies.
+template <typename T>
+__device__ __forceinline__ void cmul_ip(cplx<T> &x, const cplx<T> u) {
+    if constexpr (sizeof(T) == 4) {
+        const float t = u.im * x.im;
+        const float v = u.im * x.re;
+        asm("v_fma_f32 %0, %1, %0, -%2" : "+v"(x.re) : "v"(u.re), "v"(t));
+        asm("v_fma_f32 %0, %1, %0, %2" : "+v"(x.im) : "v"(u.re), "v"(v));
+    } else {
+        x = cmul(u, x);
+    }
+}
+
 __device__ __forceinline__ uint64_t insert_zero(uint64_t x, int q) {
     uint64_t lo = x & ((1ull << q) - 1);
     return ((x >> q) << (q + 1)) | lo;
@@ -157,7 +174,7 @@ __device__ __forceinline__ void pair_form(cplx<T> &x, cplx<T> &y, const Mat2<T> 
         x.re = fma(-t, b.re, a.re); x.im = fma(-t, b.im, a.im);
         y.re = fma(t, a.re, b.re); y.im = fma(t, a.im, b.im);
     } else {                                   // F_PHASE
-        y = cmul(u.m[3], b);
+        cmul_ip(y, u.m[3]);
     }
 }
 
@@ -267,7 +284,7 @@ __device__ __forceinline__ void lane_gate_f(cplx<T> (&a)[NR], const Mat2<T> &u, 
         f.re = hi ? u.m[3].re : (T)1;
         f.im = hi ? u.m[3].im : (T)0;
 #pragma unroll
-        for (int r = 0; r < NR; r++) a[r] = cmul(f, a[r]);
+        for (int r = 0; r < NR; r++) cmul_ip(a[r], f);
         return;
     }
     cplx<T> cs, cp;
@@ -459,7 +476,7 @@ __device__ __forceinline__ void regtile_op(cplx<T> (&a)[NR], int kind, int arg, 
         if (any) {
 #pragma unroll
             for (int r = 0; r < NR; r++)
-                if ((rs >> r) & 1) a[r] = cmul(f, a[r]);
+                if ((rs >> r) & 1) cmul_ip(a[r], f);
         }
     }
 }
